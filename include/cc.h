@@ -1,0 +1,219 @@
+/*
+ * cc.h -- colourful subgraph counting for queries of treewidth <= 2 on one
+ * MI355X (gfx950) GPU.
+ *
+ * The library computes, for a data graph G (n vertices, m undirected edges)
+ * and a query Q with k nodes, the number of colourful matches of Q in G
+ * under random colourings of G with k colours (Preliminaries: matches are
+ * injective, edge-preserving maps V_Q -> V_G; a match is colourful when its
+ * k images carry k distinct colours), and the colour-coding estimate of the
+ * number of matches scaled to subgraph copies (Section 2: (k^k/k!) times the
+ * mean colourful count is an unbiased estimate of n(G,Q); dividing by aut(Q)
+ * turns matches into copies).
+ *
+ * The counts come from the degree-based dynamic program of Section 4: the
+ * query is decomposed into leaf-edge and cycle blocks (Section 4.1), and each
+ * cycle is solved by partitioning its colourful matches by the highest
+ * matched vertex in the degree order (Eq. (1)) and joining high-starting
+ * path tables (NodeJoin / EdgeJoin, Section 4.4).  All arithmetic is exact
+ * unsigned integer arithmetic; overflow is detected, never wrapped.
+ *
+ * Conventions for every call:
+ *   - Every call returns a cc_status; on error the outputs are left untouched
+ *     unless stated otherwise, and cc_last_error() describes the failure.
+ *   - The caller owns every buffer it passes.  Input arrays are copied before
+ *     the call returns; outputs are written before it returns (all calls are
+ *     synchronous with respect to the host, even when a stream is given).
+ *   - Arrays documented "host" must be host memory.  `stream` is a
+ *     hipStream_t (or NULL for the library's own stream); the device work of
+ *     a call is ordered on that stream.
+ *   - Handles are opaque, immutable after creation, and freed only by the
+ *     matching *_destroy call.  A graph may be shared by concurrent calls on
+ *     different streams; a cc_server is not thread-safe.
+ *   - Vertex ids are int32 in [0, n); colours are uint8 in [0, k); counts are
+ *     uint64.
+ */
+#ifndef CC_H
+#define CC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CC_OK = 0,
+  CC_E_ARG = 1,                /* a pointer is null, a size is negative or out of range */
+  CC_E_GRAPH = 2,              /* malformed CSR: not symmetric, self-loop, duplicate edge, id out of range */
+  CC_E_QUERY_TW = 3,           /* no decomposition into blocks: the query has treewidth > 2 (Lemma 4.1) */
+  CC_E_QUERY_DISCONNECTED = 4, /* the query is not connected */
+  CC_E_K_RANGE = 5,            /* k < 2 or k > 12 */
+  CC_E_UNSUPPORTED = 6,        /* every decomposition needs a pair-keyed table (two non-adjacent boundary nodes) */
+  CC_E_NOMEM = 7,              /* the work does not fit the device memory budget */
+  CC_E_DEVICE = 8,             /* a HIP runtime call failed */
+  CC_E_BUSY = 9                /* a server's request table is full */
+} cc_status;
+
+typedef struct cc_graph_s *cc_graph;
+typedef struct cc_query_s *cc_query;
+typedef struct cc_server_s *cc_server;
+
+/* An unsigned 128-bit integer, lo + 2^64 * hi. */
+typedef struct {
+  uint64_t lo, hi;
+} cc_u128;
+
+/* Tuning knobs; zero means "choose automatically". */
+typedef struct {
+  int32_t group_sources;   /* high-degree sources processed together per launch (<= 64) */
+  int32_t trial_group;     /* colourings processed together */
+  int32_t light_max_keys;  /* per-level key capacity of the one-workgroup-per-source path */
+  int32_t use_graphs;      /* 1: capture the launch sequence of a solve in a hipGraph and replay it */
+} cc_tuning;
+
+/* ------------------------------------------------------------------ graphs */
+
+/* Flags for cc_graph_create. */
+#define CC_GRAPH_CLEAN 1u         /* drop self-loops and duplicate edges instead of failing */
+#define CC_GRAPH_REVERSE_TIES 2u  /* break degree ties by larger id first (the total is unchanged, Eq. (1)) */
+
+/*
+ * Make a data graph resident on the current device.
+ *   n        number of vertices, 1 <= n < 2^31.
+ *   row_ptr  host, int64[n+1], row_ptr[0] = 0, non-decreasing.
+ *   col      host, int32[row_ptr[n]]: neighbours of v are col[row_ptr[v] .. row_ptr[v+1]).
+ *            Every undirected edge {u,v} appears as v in u's row and u in v's row.
+ * The library orders vertices by (degree, id) ascending (Section 4.3, degree
+ * ordering), relabels them by that rank and sorts every neighbour list, so the
+ * lower neighbours of a vertex form a prefix of its list.
+ * Errors: CC_E_ARG, CC_E_GRAPH (see CC_GRAPH_CLEAN), CC_E_NOMEM, CC_E_DEVICE.
+ */
+cc_status cc_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
+                          void *stream, cc_graph *out);
+cc_status cc_graph_destroy(cc_graph g);
+/* n, m (undirected edges) and the maximum degree of a resident graph. */
+cc_status cc_graph_info(cc_graph g, int64_t *n, int64_t *m, int64_t *max_degree);
+
+/* ------------------------------------------------------------------ queries */
+
+/*
+ * Plan a query: k nodes 0..k-1, num_edges undirected edges given as pairs in
+ * `edges` (host, int32[2*num_edges]).  The query must be simple and connected
+ * with 2 <= k <= 12.  The planner enumerates decomposition trees (Section 4.1,
+ * Cases 1-3) and picks one by the heuristic of Section 5 (shortest longest
+ * cycle, then fewest boundary nodes, then fewest annotations), among the trees
+ * whose two-boundary blocks have adjacent boundary nodes.
+ * Errors: CC_E_ARG, CC_E_K_RANGE, CC_E_QUERY_DISCONNECTED, CC_E_QUERY_TW, CC_E_UNSUPPORTED.
+ */
+cc_status cc_query_create(int32_t k, int32_t num_edges, const int32_t *edges, cc_query *out);
+cc_status cc_query_destroy(cc_query q);
+/* aut(Q) (Preliminaries), the number of blocks and the longest cycle of the chosen tree. */
+cc_status cc_query_info(cc_query q, uint64_t *aut, int32_t *num_blocks, int32_t *longest_cycle);
+/*
+ * Describe the chosen decomposition tree as ints (host buffer `out`, capacity
+ * `cap`): [nblocks, then per block: kind (0 leaf, 1 cycle, 2 root cycle,
+ * 3 root singleton), size of its subquery, L, nodes[L], nboundary, boundary[],
+ * nchildren, children[]].  *len receives the number of ints needed.
+ */
+cc_status cc_query_plan(cc_query q, int32_t *out, int32_t cap, int32_t *len);
+
+/* Device bytes a count of `trials` colourings would use (tables and frontiers). */
+cc_status cc_footprint(cc_graph g, cc_query q, int32_t trials, uint64_t *bytes);
+
+/* ------------------------------------------------------------------ colourings */
+
+/*
+ * The colouring contract (the paper asks only for uniform random colours,
+ * Preliminaries): for trial t, chi_t(v) = ((mix(mix(seed + t) ^ v) >> 32) * k) >> 32
+ * where v is the caller's (original) vertex id and mix is the splitmix64
+ * output function.  Computed on the device; `out` is host, uint8[n], indexed
+ * by original vertex id.
+ */
+cc_status cc_colors(cc_graph g, int32_t k, uint64_t seed, int32_t trial, uint8_t *out);
+
+/* ------------------------------------------------------------------ counting */
+
+/*
+ * Count colourful matches of q in g for `trials` colourings drawn by the
+ * contract above from `seed` (trial t uses seed + t).
+ *   counts    host, uint64[trials]: exact counts; UINT64_MAX when overflow[t] = 1.
+ *   overflow  host, uint8[trials]: 1 if the count is >= 2^64 or a table entry
+ *             left 64 bits during the computation (sticky per trial).
+ *   exact     host, cc_u128[trials] or NULL: the exact count whenever no table
+ *             entry overflowed (also when only the final sum exceeds 2^64);
+ *             {UINT64_MAX, UINT64_MAX} otherwise.
+ *   estimate  host, double or NULL: (sum_t N_t) * k^k / (trials * k! * aut(q)),
+ *             from the exact sums, rounded once to double; NaN if any trial
+ *             overflowed.
+ * Errors: CC_E_ARG, CC_E_NOMEM, CC_E_DEVICE.
+ */
+cc_status cc_count(cc_graph g, cc_query q, uint64_t seed, int32_t trials, uint64_t *counts,
+                   uint8_t *overflow, cc_u128 *exact, double *estimate, void *stream);
+
+/*
+ * As cc_count, with the colourings given: `colors` is host, uint8[trials*n],
+ * trial-major, indexed by original vertex id, values in [0, k).
+ * `per_source` (host, cc_u128[trials*n] or NULL) receives, for a query whose
+ * root block is a cycle, the count of colourful matches whose highest root
+ * cycle vertex (in the degree order) is each vertex, indexed by original id;
+ * for a singleton root, each vertex's share of the root sum.
+ * Errors: as cc_count, plus CC_E_ARG for a colour >= k.
+ */
+cc_status cc_count_colors(cc_graph g, cc_query q, int32_t trials, const uint8_t *colors,
+                          uint64_t *counts, uint8_t *overflow, cc_u128 *exact, cc_u128 *per_source,
+                          void *stream);
+
+/*
+ * Batched form: nq queries on one graph, query i with trials[i] colourings
+ * from seeds[i].  All colourings of all queries are solved together: trials
+ * form the batch dimension of every launch and the launch sequence is
+ * captured once in a hipGraph and replayed (tuning->use_graphs).
+ *   counts / overflow  host, concatenated per query in order (sum of trials[i]).
+ *   estimates          host, double[nq] or NULL.
+ *   tuning             NULL for automatic choices.
+ * Errors: as cc_count.
+ */
+cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint64_t *seeds,
+                         const int32_t *trials, uint64_t *counts, uint8_t *overflow, double *estimates,
+                         const cc_tuning *tuning, void *stream);
+
+/* ------------------------------------------------------------------ serving */
+
+/*
+ * A request loop over resident graphs.  Requests (graph, query, seed, trials)
+ * are admitted while their device footprint fits the budget and fewer than
+ * `max_inflight` are running; admitted requests run concurrently on a pool of
+ * streams (continuous batching: a request arriving while others run starts as
+ * soon as a stream slot and memory are free).  Results are identical to
+ * cc_count on the same arguments.
+ */
+cc_status cc_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, cc_server *out);
+/* Register a resident graph; the server does not take ownership. */
+cc_status cc_server_add_graph(cc_server s, cc_graph g, int32_t *graph_id);
+/* Enqueue a request; the query must outlive it.  CC_E_BUSY if the request table is full. */
+cc_status cc_server_submit(cc_server s, int32_t graph_id, cc_query q, uint64_t seed, int32_t trials,
+                           uint64_t *ticket);
+/*
+ * Poll a ticket: *done = 1 when finished, then counts/overflow (host,
+ * [trials]) and *estimate are filled and *latency_s is completion minus
+ * submission time.  Any output pointer may be NULL.  A finished ticket is
+ * released by the poll that reports it.
+ */
+cc_status cc_server_poll(cc_server s, uint64_t ticket, int32_t *done, uint64_t *counts, uint8_t *overflow,
+                         double *estimate, double *latency_s);
+/* Block until every submitted request has finished. */
+cc_status cc_server_drain(cc_server s);
+cc_status cc_server_destroy(cc_server s);
+
+/* ------------------------------------------------------------------ errors */
+
+const char *cc_status_str(cc_status st);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC_H */

@@ -1,0 +1,173 @@
+// Internal declarations shared by the host parts of the library (planner,
+// graph residency, executor, API, server).  Device code lives in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cc.h"
+
+namespace cc {
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  cc_status st;
+  std::string msg;
+};
+[[noreturn]] void fail(cc_status st, const std::string &msg);
+void set_last_error(const std::string &msg);
+#define HIP_CHECK(x)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (x);                                                               \
+    if (_e != hipSuccess)                                                              \
+      ::cc::fail(CC_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(_e));          \
+  } while (0)
+
+// ------------------------------------------------------------------ planner
+enum BlockKind { BK_LEAF = 0, BK_CYCLE = 1, BK_ROOT_CYCLE = 2, BK_ROOT_SINGLE = 3 };
+
+// A block of the decomposition tree (Section 4.1).  For a cycle, nodes are
+// a_0..a_{L-1} in cycle order; edge i joins nodes[i] and nodes[i+1 mod L].
+// For a leaf, nodes = {a, b} with b the removed leaf and a the boundary.
+struct PBlock {
+  BlockKind kind;
+  std::vector<int> nodes;
+  std::vector<int> node_child;      // per node: child block annotating it, or -1
+  std::vector<int> edge_child;      // per edge: child block annotating it, or -1 (a data edge)
+  std::vector<char> edge_first_lo;  // per annotated edge: the child's first boundary is nodes[i]
+  std::vector<int> boundary;        // ordered boundary nodes (first, second)
+  int size = 0;                     // |SQ(B)|: number of query nodes in the subquery
+  int single_child = -1;            // BK_ROOT_SINGLE: the block annotating the last node
+};
+
+// Frontier program of one cycle block (run once per group of sources).
+enum OpKind {
+  OP_INIT = 0,   // dst[x] = A_h[u] (x) E(u,x), x a lower neighbour of u
+  OP_NJ = 1,     // dst[v] = a[v] (x) A[v]                      (NodeJoin)
+  OP_EJ = 2,     // dst[w] = sum_{v in N(w), v < u} a[v] (x) E(v,w)   (EdgeJoin)
+  OP_AXPY = 3,   // dst += w * a   (dst fresh on its first AXPY)
+  OP_MROOT = 4,  // count += w * sum_v a[v] (x) b[v], signatures covering all k colours
+  OP_MU = 5,     // U[u]  += w * sum_v a[v] (x) b[v]
+  OP_MV = 6,     // U[v]  += w * a[v] (x) b[v]
+  OP_MEDGE = 7,  // T[x,y] += w * a[x] (x) E(x,y) (x) b[y]
+  OP_MEDGE_T = 8 // T[u,y] += w * A[u] (x) E(u,y) (x) b[y]   (or T[y,u] when swapped)
+};
+
+struct Op {
+  OpKind kind;
+  int dst = -1, a = -1, b = -1;  // frontier registers
+  int tab = -1;                  // child block of the joined edge (INIT/EJ/MEDGE*), node (NJ), -1 = none
+  int tab_src_first = 0;         // edge tables: the traversal's source end is the child's first boundary
+  int ntab = -1;                 // INIT / MEDGE_T: node table joined at u (a_h's block), or -1
+  uint64_t w = 1;                // weight / multiplicity
+  int s = 0;                     // signature size of dst (merges: of the output)
+  int first = 0;                 // AXPY: dst is fresh (overwrite); MEDGE*: x-end is the table's first boundary
+  int swapped = 0;               // MEDGE_T: u is the image of the second boundary
+};
+
+struct Program {
+  std::vector<Op> ops;
+  std::vector<int> reg_s;        // signature size per register
+  std::vector<int> last_use;     // op index of each register's last use
+};
+
+struct Plan {
+  int k = 0;
+  std::vector<std::pair<int, int>> edges;
+  std::vector<PBlock> blocks;    // children before parents; the root is last
+  std::vector<Program> programs; // per block (cycles only)
+  uint64_t aut = 1;
+  int longest_cycle = 0;
+  int sum_boundary = 0;
+  int num_annotations = 0;
+};
+
+// Build the plan; throws Error (via fail) on invalid or unsupported queries.
+Plan make_plan(int k, const std::vector<std::pair<int, int>> &edges);
+// Flatten the tree for cc_query_plan.
+std::vector<int32_t> describe_plan(const Plan &p);
+
+// binomial coefficient
+inline int64_t binom(int n, int r) {
+  if (r < 0 || r > n || n < 0) return 0;
+  int64_t c = 1;
+  for (int i = 1; i <= r; i++) c = c * (n - r + i) / i;
+  return c;
+}
+// Slots of a table: unary (one key vertex) or binary (two key vertices / path key).
+inline int64_t slots_unary(int k, int s) { return binom(k - 1, s - 1); }
+inline int64_t slots_pair(int k, int s) { return binom(k - 2, s - 2); }
+
+// ------------------------------------------------------------------ graph
+struct DevGraph {
+  int64_t n = 0, m2 = 0;      // vertices, directed slots (2m)
+  int64_t max_degree = 0;
+  uint32_t flags = 0;
+  // host copies (rank order)
+  std::vector<int64_t> h_rp;
+  std::vector<int32_t> h_col;
+  std::vector<int32_t> h_orig;      // rank -> original id
+  std::vector<int32_t> h_rank;      // original id -> rank
+  std::vector<int32_t> h_lowcnt;    // number of lower neighbours
+  std::vector<int64_t> h_r2;        // two-step high-start reach estimate per source
+  // device copies
+  int64_t *rp = nullptr;
+  int32_t *col = nullptr;
+  int64_t *rev = nullptr;
+  int32_t *orig = nullptr;
+  int32_t *lowcnt = nullptr;
+  int device = 0;
+  ~DevGraph();
+};
+
+std::unique_ptr<DevGraph> make_graph(int64_t n, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
+                                     hipStream_t stream);
+
+// ------------------------------------------------------------------ executor
+struct CountResult {
+  std::vector<u128> exact;        // per trial
+  std::vector<uint8_t> overflow;  // per trial
+};
+
+struct ExecOptions {
+  int group_sources = 0;
+  int trial_group = 0;
+  int light_max_keys = 0;
+  int use_graphs = 0;
+  uint64_t mem_budget = 0;        // bytes; 0 = from the device's free memory
+};
+
+// Colours in rank order for `trials` trials: either from (seed) by the
+// contract, or from host colours indexed by original id.
+struct ColourSource {
+  bool from_seed = true;
+  uint64_t seed = 0;
+  const uint8_t *host = nullptr;  // trials * n, original ids
+};
+
+CountResult run_count(const DevGraph &g, const Plan &p, int trials, const ColourSource &cs,
+                      const ExecOptions &opt, hipStream_t stream, std::vector<u128> *per_source);
+
+uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt);
+
+// Device colouring (rank order) for one trial, copied to host by original id.
+void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t stream);
+
+double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf);
+
+}  // namespace cc
+
+// opaque handle types of the C ABI
+struct cc_graph_s {
+  std::unique_ptr<cc::DevGraph> g;
+};
+struct cc_query_s {
+  cc::Plan plan;
+};

@@ -1,0 +1,425 @@
+// Executor: runs a plan over a resident graph for a batch of colourings.
+//
+// Blocks are solved bottom-up (the overall algorithm of Section 4.2): a leaf
+// block by one per-vertex kernel, a cycle block by running its frontier
+// program (see planner.cpp) for every group of sources, the root by a final
+// reduction.  Colourings are the batch dimension of every launch.
+//
+// Sources of a cycle block are the vertices with at least two lower
+// neighbours (both cycle neighbours of the highest vertex are lower).  They
+// are taken in decreasing rank, so a group's frontier vertices all lie below
+// the rank of its first source.  The highest-reaching sources (by their
+// two-step reach) run in dense groups, where every (vertex, source) pair is a
+// potential entry and the EdgeJoin pulls over all vertices; the rest run in
+// sparse groups, whose registers keep lists of their live entries.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "cc_internal.h"
+#include "kernels.h"
+
+namespace cc {
+
+namespace {
+
+struct DevMem {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  explicit DevMem(size_t b) { alloc(b); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 8;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      fail(CC_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevMem() { release(); }
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  template <typename T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+struct RegBuf {
+  DevMem val, act, list, cnt;
+  int C = 0, s = 0;
+  bool owns_act = true;
+  int alias = -1;  // shares act/list with this register (NodeJoin output)
+};
+
+int table_C(const Plan &p, int blk) {
+  const PBlock &B = p.blocks[blk];
+  if (B.boundary.size() == 2) return (int)slots_pair(p.k, B.size);
+  return (int)slots_unary(p.k, B.size);
+}
+
+bool is_edge_table(const Plan &p, int blk) { return p.blocks[blk].boundary.size() == 2; }
+
+struct Sizing {
+  int T;             // trials per group
+  int B_dense;       // sources per dense group
+  int B_sparse;      // sources per sparse group
+  int64_t dense_cut; // number of leading sources run dense
+};
+
+uint64_t program_bytes_per_vb(const Plan &p, int T) {
+  // bytes per (vertex, source) pair over all registers of all programs (max)
+  uint64_t best = 0;
+  for (size_t i = 0; i < p.blocks.size(); i++) {
+    const Program &P = p.programs[i];
+    uint64_t b = 0;
+    for (int s : P.reg_s) b += (uint64_t)slots_pair(p.k, s) * T * 8 + 1 + 8;
+    best = std::max(best, b);
+  }
+  return best;
+}
+
+uint64_t table_bytes(const DevGraph &g, const Plan &p, int T) {
+  uint64_t b = 0;
+  for (size_t i = 0; i < p.blocks.size(); i++) {
+    const PBlock &B = p.blocks[i];
+    if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE) continue;
+    uint64_t keys = is_edge_table(p, (int)i) ? (uint64_t)g.m2 : (uint64_t)g.n;
+    b += keys * (uint64_t)T * table_C(p, (int)i) * 8;
+  }
+  return b;
+}
+
+uint64_t free_bytes() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
+  return (uint64_t)fr;
+}
+
+Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt, uint64_t budget) {
+  Sizing z{};
+  z.T = opt.trial_group > 0 ? std::min(opt.trial_group, 64) : std::min(trials, 64);
+  if (z.T < 1) z.T = 1;
+  for (;;) {
+    uint64_t tabs = table_bytes(g, p, z.T);
+    uint64_t per_vb = program_bytes_per_vb(p, z.T);
+    uint64_t n = (uint64_t)std::max<int64_t>(1, g.n);
+    uint64_t left = budget > tabs ? budget - tabs : 0;
+    int64_t B = per_vb ? (int64_t)(left / (per_vb * n)) : 64;
+    if (B >= 1 || z.T == 1) {
+      B = std::max<int64_t>(1, std::min<int64_t>(B, 64));
+      if (opt.group_sources > 0) B = std::min<int64_t>(B, opt.group_sources);
+      z.B_dense = (int)B;
+      z.B_sparse = (int)B;
+      if (tabs + per_vb * n * B > budget) fail(CC_E_NOMEM, "plan does not fit the device memory budget");
+      return z;
+    }
+    z.T = std::max(1, z.T / 2);
+  }
+}
+
+}  // namespace
+
+uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt) {
+  int T = std::min(std::max(trials, 1), 64);
+  if (opt.trial_group > 0) T = std::min(T, opt.trial_group);
+  uint64_t tabs = table_bytes(g, p, T);
+  uint64_t per_vb = program_bytes_per_vb(p, T);
+  int B = opt.group_sources > 0 ? std::min(opt.group_sources, 64) : 64;
+  return tabs + per_vb * (uint64_t)g.n * B + (uint64_t)g.n * T;
+}
+
+void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t st) {
+  DevMem d(g.n);
+  launch_colour(g.orig, g.n, k, seed, trial, 1, d.as<uint8_t>(), st);
+  HIP_CHECK(hipGetLastError());
+  std::vector<uint8_t> h(g.n);
+  HIP_CHECK(hipMemcpyAsync(h.data(), d.p, g.n, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int64_t r = 0; r < g.n; r++) out[g.h_orig[r]] = h[r];
+}
+
+double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf) {
+  if (exact.empty()) return NAN;
+  for (auto o : ovf)
+    if (o) return NAN;
+  u128 sum = 0;
+  for (auto x : exact) sum += x;
+  // (sum * k^k) / (T * k! * aut), exact numerator and denominator in 128 bits
+  // when they fit, else in long double.
+  long double num = (long double)sum, den = (long double)exact.size() * (long double)p.aut;
+  for (int i = 1; i <= p.k; i++) {
+    num *= p.k;
+    den *= i;
+  }
+  u128 kk = 1, kf = 1;
+  bool fits = true;
+  for (int i = 1; i <= p.k; i++) {
+    kk *= (u128)p.k;
+    kf *= (u128)i;
+  }
+  u128 d128 = kf * (u128)exact.size() * (u128)p.aut;
+  if (sum != 0 && kk > (~(u128)0) / sum) fits = false;
+  if (fits) {
+    u128 n128 = sum * kk;
+    u128 q = n128 / d128, r = n128 % d128;
+    return (double)((long double)q + (long double)r / (long double)d128);
+  }
+  return (double)(num / den);
+}
+
+// ------------------------------------------------------------------ main
+CountResult run_count(const DevGraph &g, const Plan &p, int trials, const ColourSource &cs, const ExecOptions &opt,
+                      hipStream_t st, std::vector<u128> *per_source) {
+  if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
+  HIP_CHECK(hipSetDevice(g.device));
+  const int k = p.k;
+  uint64_t budget = opt.mem_budget ? opt.mem_budget : (uint64_t)(free_bytes() * 0.85);
+  Sizing z = choose(g, p, trials, opt, budget);
+  const int T = z.T;
+
+  CountResult res;
+  res.exact.assign(trials, 0);
+  res.overflow.assign(trials, 0);
+  if (per_source) per_source->assign((size_t)trials * g.n, 0);
+
+  GraphDev gd{g.rp, g.col, g.rev, g.n, g.m2};
+
+  // sources: lowcnt >= 2, descending rank
+  std::vector<int32_t> sources;
+  for (int64_t r = g.n - 1; r >= 0; r--)
+    if (g.h_lowcnt[r] >= 2) sources.push_back((int32_t)r);
+  // dense cut: sources whose two-step reach covers a good part of their prefix
+  int64_t ndense = 0;
+  for (size_t i = 0; i < sources.size(); i++) {
+    int64_t u = sources[i];
+    if (g.h_r2[u] * 4 >= u && u > 4096) ndense = (int64_t)i + 1;
+    else break;
+  }
+  // groups
+  struct Grp {
+    int64_t lo, hi;
+    bool dense;
+  };
+  std::vector<Grp> groups;
+  for (int64_t i = 0; i < ndense; i += z.B_dense) groups.push_back({i, std::min<int64_t>(ndense, i + z.B_dense), true});
+  for (int64_t i = ndense; i < (int64_t)sources.size(); i += z.B_sparse)
+    groups.push_back({i, std::min<int64_t>((int64_t)sources.size(), i + z.B_sparse), false});
+  int Bmax = std::max(z.B_dense, z.B_sparse);
+  int64_t nlim_max = sources.empty() ? 1 : sources[0];
+  if (nlim_max < 1) nlim_max = 1;
+
+  DevMem d_src(sizeof(int32_t) * std::max<size_t>(1, sources.size()));
+  if (!sources.empty())
+    HIP_CHECK(hipMemcpyAsync(d_src.p, sources.data(), sizeof(int32_t) * sources.size(), hipMemcpyHostToDevice, st));
+  DevMem d_col((size_t)g.n * T);
+  DevMem d_sum(sizeof(uint64_t) * 2 * 64), d_ovf(sizeof(uint32_t) * 64);
+  DevMem d_per(per_source ? sizeof(uint64_t) * 2 * (size_t)g.n * T : 8);
+  DevMem d_hcol;
+  if (!cs.from_seed) d_hcol.alloc((size_t)g.n * T);
+
+  // child tables
+  std::vector<DevMem> tabs(p.blocks.size());
+  for (size_t i = 0; i < p.blocks.size(); i++) {
+    const PBlock &B = p.blocks[i];
+    if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE) continue;
+    int64_t keys = is_edge_table(p, (int)i) ? g.m2 : g.n;
+    tabs[i].alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, keys) * T * table_C(p, (int)i));
+  }
+  auto tabdev = [&](int blk) {
+    TabDev t{nullptr, 0, 0};
+    if (blk >= 0) {
+      t.val = tabs[blk].as<uint64_t>();
+      t.C = table_C(p, blk);
+      t.s = p.blocks[blk].size;
+    }
+    return t;
+  };
+
+  // registers: one pool sized for the largest program
+  size_t nregs = 0;
+  for (auto &P : p.programs) nregs = std::max(nregs, P.reg_s.size());
+  std::vector<RegBuf> regs(nregs);
+  auto ensure_reg = [&](int r, int s) {
+    RegBuf &R = regs[r];
+    int C = (int)slots_pair(k, s);
+    size_t vb = sizeof(uint64_t) * (size_t)nlim_max * Bmax * T * C;
+    if (R.val.bytes < vb) R.val.alloc(vb);
+    size_t ab = ((size_t)nlim_max * Bmax + 3) & ~(size_t)3;
+    if (R.act.bytes < ab) {
+      R.act.alloc(ab);
+      launch_fill_u8(R.act.as<uint8_t>(), (int64_t)ab, st);
+    }
+    if (R.list.bytes < sizeof(int64_t) * (size_t)nlim_max * Bmax) R.list.alloc(sizeof(int64_t) * (size_t)nlim_max * Bmax);
+    if (!R.cnt.p) {
+      R.cnt.alloc(sizeof(uint32_t));
+      HIP_CHECK(hipMemsetAsync(R.cnt.p, 0, sizeof(uint32_t), st));
+    }
+    R.C = C;
+    R.s = s;
+  };
+
+  const int32_t *lowcnt_d = g.lowcnt;
+
+  for (int t0 = 0; t0 < trials; t0 += T) {
+    int Tg = std::min(T, trials - t0);
+    // colours of this trial group, rank order
+    if (cs.from_seed) {
+      launch_colour(g.orig, g.n, k, cs.seed, t0, Tg, d_col.as<uint8_t>(), st);
+    } else {
+      HIP_CHECK(hipMemcpyAsync(d_hcol.p, cs.host + (size_t)t0 * g.n, (size_t)g.n * Tg, hipMemcpyHostToDevice, st));
+      launch_permute_colours(d_hcol.as<uint8_t>(), g.orig, g.n, Tg, d_col.as<uint8_t>(), st);
+    }
+    const uint8_t *colr = d_col.as<uint8_t>();
+    HIP_CHECK(hipMemsetAsync(d_sum.p, 0, d_sum.bytes, st));
+    HIP_CHECK(hipMemsetAsync(d_ovf.p, 0, d_ovf.bytes, st));
+    if (per_source) HIP_CHECK(hipMemsetAsync(d_per.p, 0, d_per.bytes, st));
+    AccDev acc{d_sum.as<uint64_t>(), d_ovf.as<uint32_t>(), per_source ? d_per.as<uint64_t>() : nullptr};
+    uint32_t *ovf = d_ovf.as<uint32_t>();
+
+    for (size_t bi = 0; bi < p.blocks.size(); bi++) {
+      const PBlock &B = p.blocks[bi];
+      if (B.kind == BK_LEAF) {
+        int a = B.nodes[0];
+        (void)a;
+        int ec = B.edge_child[0];
+        launch_leaf(gd, Tg, k, colr, tabdev(B.node_child[0]), tabdev(ec), ec >= 0 ? B.edge_first_lo[0] : 0,
+                    tabdev(B.node_child[1]), tabs[bi].as<uint64_t>(), B.size, table_C(p, (int)bi), ovf, st);
+        HIP_CHECK(hipGetLastError());
+        continue;
+      }
+      if (B.kind == BK_ROOT_SINGLE) {
+        TabDev u = tabdev(B.single_child);
+        launch_root_single(g.n, Tg, u, acc, st);
+        HIP_CHECK(hipGetLastError());
+        continue;
+      }
+      // cycle block
+      const Program &P = p.programs[bi];
+      uint64_t *out = nullptr;
+      int C_out = 0;
+      if (B.kind == BK_CYCLE) {
+        out = tabs[bi].as<uint64_t>();
+        C_out = table_C(p, (int)bi);
+        int64_t keys = is_edge_table(p, (int)bi) ? g.m2 : g.n;
+        launch_fill_u64(out, keys * Tg * C_out, st);
+      }
+      for (size_t r = 0; r < P.reg_s.size(); r++) ensure_reg((int)r, P.reg_s[r]);
+      // registers whose activity/list belong to another (NodeJoin outputs)
+      std::vector<int> alias(P.reg_s.size(), -1);
+      for (auto &op : P.ops)
+        if (op.kind == OP_NJ) alias[op.dst] = alias[op.a] >= 0 ? alias[op.a] : op.a;
+      auto regdev = [&](int r) {
+        RegDev d;
+        int own = alias[r] >= 0 ? alias[r] : r;
+        d.val = regs[r].val.as<uint64_t>();
+        d.act = regs[own].act.as<uint8_t>();
+        d.list = regs[own].list.as<int64_t>();
+        d.cnt = regs[own].cnt.as<uint32_t>();
+        d.C = (int)slots_pair(k, P.reg_s[r]);
+        d.s = P.reg_s[r];
+        return d;
+      };
+      bool prev_dense = false;
+      for (auto &G : groups) {
+        GroupDev grp;
+        grp.src = d_src.as<int32_t>() + G.lo;
+        grp.B = (int)(G.hi - G.lo);
+        grp.T = Tg;
+        grp.k = k;
+        grp.n_lim = sources[G.lo];
+        grp.dense = G.dense ? 1 : 0;
+        int max_low = 0;
+        for (int64_t i = G.lo; i < G.hi; i++) max_low = std::max(max_low, g.h_lowcnt[sources[i]]);
+        if (!G.dense && prev_dense) {
+          // activity bytes hold dense-mode leftovers: clear them all
+          for (size_t r = 0; r < P.reg_s.size(); r++)
+            if (alias[r] < 0) launch_fill_u8(regs[r].act.as<uint8_t>(), (int64_t)regs[r].act.bytes, st);
+        }
+        prev_dense = G.dense;
+        for (size_t oi = 0; oi < P.ops.size(); oi++) {
+          const Op &op = P.ops[oi];
+          switch (op.kind) {
+            case OP_INIT: {
+              RegDev d = regdev(op.dst);
+              if (G.dense) launch_fill_u8(d.act, grp.n_lim * grp.B, st);
+              launch_init(gd, grp, lowcnt_d, max_low, colr, d, tabdev(op.tab), op.tab_src_first, tabdev(op.ntab),
+                          ovf, st);
+              break;
+            }
+            case OP_NJ:
+              launch_nj(gd, grp, colr, regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
+              break;
+            case OP_EJ: {
+              RegDev a = regdev(op.a), d = regdev(op.dst);
+              if (!G.dense) launch_mark(gd, grp, a, d, st);
+              launch_ej(gd, grp, colr, a, d, tabdev(op.tab), op.tab_src_first, ovf, st);
+              break;
+            }
+            case OP_AXPY:
+              launch_axpy(grp, regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
+              break;
+            case OP_MROOT:
+              launch_mroot(grp, g.n, colr, regdev(op.a), regdev(op.b), op.w, acc, st);
+              break;
+            case OP_MU:
+              launch_mu(grp, g.n, colr, regdev(op.a), regdev(op.b), op.w, out, op.s, C_out, ovf, st);
+              break;
+            case OP_MV:
+              launch_mv(grp, g.n, colr, regdev(op.a), regdev(op.b), op.w, out, op.s, C_out, ovf, st);
+              break;
+            case OP_MEDGE:
+              launch_medge(gd, grp, colr, regdev(op.a), regdev(op.b), tabdev(op.tab), op.tab_src_first, op.first,
+                           op.w, out, op.s, C_out, ovf, st);
+              break;
+            case OP_MEDGE_T:
+              launch_medge_t(gd, grp, colr, lowcnt_d, max_low, tabdev(op.ntab), regdev(op.b), tabdev(op.tab),
+                             op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
+              break;
+          }
+          HIP_CHECK(hipGetLastError());
+        }
+        if (!G.dense) {
+          for (size_t r = 0; r < P.reg_s.size(); r++)
+            if (alias[r] < 0) launch_clear_list(regdev((int)r), grp.B, st);
+        }
+      }
+      if (prev_dense) {
+        for (size_t r = 0; r < P.reg_s.size(); r++)
+          if (alias[r] < 0) launch_fill_u8(regs[r].act.as<uint8_t>(), (int64_t)regs[r].act.bytes, st);
+      }
+    }
+    // results of this trial group
+    std::vector<uint64_t> hs(2 * 64);
+    std::vector<uint32_t> ho(64);
+    HIP_CHECK(hipMemcpyAsync(hs.data(), d_sum.p, sizeof(uint64_t) * 2 * 64, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(ho.data(), d_ovf.p, sizeof(uint32_t) * 64, hipMemcpyDeviceToHost, st));
+    std::vector<uint64_t> hp;
+    if (per_source) {
+      hp.resize(2 * (size_t)g.n * Tg);
+      HIP_CHECK(hipMemcpyAsync(hp.data(), d_per.p, sizeof(uint64_t) * hp.size(), hipMemcpyDeviceToHost, st));
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int t = 0; t < Tg; t++) {
+      res.exact[t0 + t] = (u128)hs[2 * t] | ((u128)hs[2 * t + 1] << 64);
+      res.overflow[t0 + t] = ho[t] ? 1 : 0;
+    }
+    if (per_source)
+      for (int64_t r = 0; r < g.n; r++)
+        for (int t = 0; t < Tg; t++) {
+          size_t i = 2 * ((size_t)r * Tg + t);
+          (*per_source)[(size_t)(t0 + t) * g.n + g.h_orig[r]] = (u128)hp[i] | ((u128)hp[i + 1] << 64);
+        }
+  }
+  return res;
+}
+
+}  // namespace cc

@@ -1,0 +1,90 @@
+// Launch wrappers for the device kernels (kernels.hip).  Host code only sees
+// plain pointers and sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cc {
+
+// A frontier register for one group of B sources and T colourings: values
+// [v][b][t][slot] for v in [0, n_lim), activity bytes [v][b], and (sparse
+// mode) a list of active (v, b) entries encoded v*64 + b with its length.
+struct RegDev {
+  uint64_t *val;
+  uint8_t *act;
+  int64_t *list;
+  uint32_t *cnt;
+  int C;  // slots per (v, b, t)
+  int s;  // signature size
+};
+
+// The group being processed.
+struct GroupDev {
+  const int32_t *src;  // source ranks, [B]
+  int B;
+  int T;
+  int k;
+  int64_t n_lim;      // every frontier vertex is below this rank
+  int dense;          // 1: domain = all (v, b) with v < n_lim; 0: the register's list
+};
+
+struct GraphDev {
+  const int64_t *rp;
+  const int32_t *col;
+  const int64_t *rev;
+  int64_t n;
+  int64_t m2;
+};
+
+// Tables of child blocks.
+struct TabDev {
+  const uint64_t *val;  // unary: [x][t][slot]; edge: [slot e][t][slot]
+  int C;
+  int s;
+};
+
+// Per-launch outputs / accumulators.
+struct AccDev {
+  uint64_t *sum;       // per trial: lo, hi (2 x u64)
+  uint32_t *ovf;       // per trial overflow flag
+  uint64_t *per_src;   // optional [n][T] x (lo, hi) by rank, or null
+};
+
+const uint16_t *lut_device(int device);  // colex rank / unrank tables
+
+void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0, int T, uint8_t *out,
+                   hipStream_t st);
+void launch_permute_colours(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out,
+                            hipStream_t st);
+void launch_fill_u8(uint8_t *p, int64_t n, hipStream_t st);
+void launch_fill_u64(uint64_t *p, int64_t n, hipStream_t st);
+void launch_clear_list(RegDev r, int B, hipStream_t st);
+
+void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, const uint8_t *colr,
+                 RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st);
+void launch_mark(const GraphDev &g, const GroupDev &grp, RegDev a, RegDev dst, hipStream_t st);
+void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, RegDev a, RegDev dst, TabDev etab,
+               int e_src_first, uint32_t *ovf, hipStream_t st);
+void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, RegDev a, RegDev dst, TabDev ntab,
+               uint32_t *ovf, hipStream_t st);
+void launch_axpy(const GroupDev &grp, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,
+                 hipStream_t st);
+void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w,
+                  AccDev acc, hipStream_t st);
+void launch_mu(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w, uint64_t *out,
+               int s_out, int C_out, uint32_t *ovf, hipStream_t st);
+void launch_mv(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w, uint64_t *out,
+               int s_out, int C_out, uint32_t *ovf, hipStream_t st);
+void launch_medge(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, RegDev a, RegDev b, TabDev etab,
+                  int e_src_first, int out_first_is_x, uint64_t w, uint64_t *out, int s_out, int C_out,
+                  uint32_t *ovf, hipStream_t st);
+void launch_medge_t(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, const int32_t *lowcnt,
+                    int max_low, TabDev ntab, RegDev b, TabDev etab, int e_src_first, int out_first_is_u,
+                    uint64_t w, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
+void launch_leaf(const GraphDev &g, int T, int k, const uint8_t *colr, TabDev na, TabDev ea, int e_src_first,
+                 TabDev nb, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
+void launch_root_single(int64_t n, int T, TabDev u, AccDev acc, hipStream_t st);
+
+}  // namespace cc

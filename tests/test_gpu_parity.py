@@ -1,0 +1,79 @@
+"""Device parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element on the same seeded inputs.  Integer counts: bit-exact."""
+import numpy as np
+import pytest
+
+from cc_inputs import graphs, queries as Q
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_1602_04478_amd.cc")
+
+
+def _colours(n, k, trials, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, k, size=(trials, n), dtype=np.uint8)
+
+
+SHAPES = {
+    "C3": Q.cycle(3), "C4": Q.cycle(4), "C5": Q.cycle(5), "C6": Q.cycle(6), "C7": Q.cycle(7),
+    "C6+pendant": Q.cycle_pendant(6), "C4+pendant": Q.cycle_pendant(4),
+    "domino+tail": Q.domino_tail(), "star5": Q.star(5), "path4": Q.path(4), "edge": Q.path(2),
+    "chorded6": (6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 0), (0, 3)]),
+    "bowtie": (5, [(0, 1), (1, 2), (2, 0), (0, 3), (3, 4), (4, 0)]),
+    "tri+tail": (5, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4)]),
+    "C5+chord-tree": (7, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (1, 5), (5, 6)]),
+    "two4cycles-node": (7, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (4, 5), (5, 6), (6, 0)]),
+}
+
+
+@pytest.fixture(scope="module")
+def small_graphs():
+    return [graphs.erdos_renyi(60, 8.0, seed=21), graphs.chung_lu(400, 6.0, 2.2, None, seed=22),
+            graphs.erdos_renyi(25, 12.0, seed=23)]
+
+
+@pytest.mark.parametrize("name", sorted(SHAPES))
+def test_small_shapes_match_oracle(small_graphs, name):
+    k, E = SHAPES[name]
+    q = cc.Query(k, E)
+    for gi, g in enumerate(small_graphs):
+        print(f"[parity] {name} graph{gi} n={g.n} m={g.m}", flush=True)
+        dg = cc.Graph.from_csr(g)
+        col = _colours(g.n, k, 3, seed=100 + gi)
+        counts, ovf, exact = cc.count_colors(dg, q, col)
+        for t in range(3):
+            want = O.db(g, k, E, col[t])
+            assert not ovf[t]
+            assert exact[t] == want, (name, gi, t, exact[t], want)
+            assert int(counts[t]) == want
+
+
+def test_colour_contract_device_equals_oracle():
+    g = graphs.erdos_renyi(500, 6.0, seed=5)
+    dg = cc.Graph.from_csr(g)
+    for k, seed, t in ((5, 101, 0), (7, 102, 3), (12, 2**64 - 5, 1)):
+        assert np.array_equal(dg.colors(k, seed, t), O.colours(g.n, k, seed, t))
+
+
+def test_config_tiny_er1000_c5():
+    """G(n=1000, avg degree 10), 5-cycle, k = 5, colouring seed 101."""
+    g = graphs.workload_graph("er1000")
+    k, E = Q.cycle(5)
+    dg = cc.Graph.from_csr(g)
+    q = cc.Query(k, E)
+    counts, ovf, exact, est = cc.count(dg, q, 101, 1)
+    chi = O.colours(g.n, k, 101, 0)
+    want = O.db(g, k, E, chi)
+    assert want == O.brute(g, k, E, chi)
+    assert exact[0] == want and int(counts[0]) == want and not ovf[0]
+
+
+def test_reverse_ties_same_total():
+    g = graphs.chung_lu(3000, 8.0, 2.1, None, seed=31)
+    k, E = Q.cycle_pendant(6)
+    q = cc.Query(k, E)
+    a = cc.count(cc.Graph.from_csr(g), q, 7, 2)[2]
+    b = cc.count(cc.Graph.from_csr(g, cc.CC_GRAPH_REVERSE_TIES), q, 7, 2)[2]
+    assert a == b
