@@ -206,6 +206,28 @@ cc_status cc_server_poll(cc_server s, uint64_t ticket, int32_t *done, uint64_t *
 cc_status cc_server_drain(cc_server s);
 cc_status cc_server_destroy(cc_server s);
 
+/* ------------------------------------------------------------------ profiling */
+
+/*
+ * Per-kernel timing, for measurement only.  While enabled, every kernel launch
+ * of cc_count* is bracketed by HIP events on the call's stream; elapsed times
+ * are summed per kernel name, together with the algorithmic bytes of the
+ * EdgeJoin kernels (counted on the device: 4 bytes per neighbour id scanned,
+ * 1 byte per activity check, 8 bytes per slot of every gathered input vector
+ * and of every written output vector).  Enabling it slows the calls down.
+ */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double seconds;  /* summed event-measured duration */
+  double bytes;    /* algorithmic bytes (EdgeJoin only; 0 elsewhere) */
+} cc_kernel_stat;
+
+cc_status cc_profile_enable(int32_t on);
+/* Copy up to `cap` entries into `out` (host), set *len to the number of
+ * kernels recorded, and reset the statistics. */
+cc_status cc_profile_read(cc_kernel_stat *out, int32_t cap, int32_t *len);
+
 /* ------------------------------------------------------------------ errors */
 
 const char *cc_status_str(cc_status st);

@@ -21,7 +21,8 @@ STATUS = {0: "CC_OK", 1: "CC_E_ARG", 2: "CC_E_GRAPH", 3: "CC_E_QUERY_TW", 4: "CC
 EXPORTS = ["cc_graph_create", "cc_graph_destroy", "cc_graph_info", "cc_query_create", "cc_query_destroy",
            "cc_query_info", "cc_query_plan", "cc_footprint", "cc_colors", "cc_count", "cc_count_colors",
            "cc_count_batch", "cc_server_create", "cc_server_add_graph", "cc_server_submit", "cc_server_poll",
-           "cc_server_drain", "cc_server_destroy", "cc_status_str", "cc_last_error"]
+           "cc_server_drain", "cc_server_destroy", "cc_profile_enable", "cc_profile_read", "cc_status_str",
+           "cc_last_error"]
 
 
 class CCError(RuntimeError):
@@ -33,6 +34,11 @@ class CCError(RuntimeError):
 
 class U128(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -72,6 +78,8 @@ def lib():
         "cc_server_poll": [vp, u64, P(i32), vp, vp, vp, vp],
         "cc_server_drain": [vp],
         "cc_server_destroy": [vp],
+        "cc_profile_enable": [i32],
+        "cc_profile_read": [vp, i32, P(i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -274,3 +282,18 @@ class Server:
         if self.h:
             _check(lib().cc_server_destroy(self.h))
             self.h = None
+
+
+def profile_enable(on: bool = True):
+    _check(lib().cc_profile_enable(1 if on else 0))
+
+
+def profile_take():
+    """Read and reset per-kernel statistics: {name: (launches, seconds, algorithmic bytes)}."""
+    cap = 256
+    buf = (KernelStat * cap)()
+    n = ctypes.c_int32()
+    _check(lib().cc_profile_read(buf, cap, ctypes.byref(n)))
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].seconds), float(buf[i].bytes))
+            for i in range(min(n.value, cap))}
+

@@ -227,4 +227,23 @@ cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint6
   });
 }
 
+cc_status cc_profile_enable(int32_t on) {
+  return guard([&] { cc::profile_enable(on != 0); });
+}
+
+cc_status cc_profile_read(cc_kernel_stat *out, int32_t cap, int32_t *len) {
+  return guard([&] {
+    if (!len) cc::fail(CC_E_ARG, "null length");
+    auto v = cc::profile_read();
+    *len = (int32_t)v.size();
+    for (int32_t i = 0; out && i < cap && i < (int32_t)v.size(); i++) {
+      std::memset(out[i].name, 0, sizeof(out[i].name));
+      std::strncpy(out[i].name, v[i].first.c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = (uint64_t)v[i].second[0];
+      out[i].seconds = v[i].second[1];
+      out[i].bytes = v[i].second[2];
+    }
+  });
+}
+
 }  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <memory>
 #include <mutex>
@@ -11,6 +12,7 @@
 #include <vector>
 
 #include "../../include/cc.h"
+#include "kernels.h"
 
 namespace cc {
 
@@ -47,19 +49,6 @@ struct PBlock {
   int single_child = -1;            // BK_ROOT_SINGLE: the block annotating the last node
 };
 
-// Frontier program of one cycle block (run once per group of sources).
-enum OpKind {
-  OP_INIT = 0,   // dst[x] = A_h[u] (x) E(u,x), x a lower neighbour of u
-  OP_NJ = 1,     // dst[v] = a[v] (x) A[v]                      (NodeJoin)
-  OP_EJ = 2,     // dst[w] = sum_{v in N(w), v < u} a[v] (x) E(v,w)   (EdgeJoin)
-  OP_AXPY = 3,   // dst += w * a   (dst fresh on its first AXPY)
-  OP_MROOT = 4,  // count += w * sum_v a[v] (x) b[v], signatures covering all k colours
-  OP_MU = 5,     // U[u]  += w * sum_v a[v] (x) b[v]
-  OP_MV = 6,     // U[v]  += w * a[v] (x) b[v]
-  OP_MEDGE = 7,  // T[x,y] += w * a[x] (x) E(x,y) (x) b[y]
-  OP_MEDGE_T = 8 // T[u,y] += w * A[u] (x) E(u,y) (x) b[y]   (or T[y,u] when swapped)
-};
-
 struct Op {
   OpKind kind;
   int dst = -1, a = -1, b = -1;  // frontier registers
@@ -75,7 +64,9 @@ struct Op {
 struct Program {
   std::vector<Op> ops;
   std::vector<int> reg_s;        // signature size per register
+  std::vector<int> reg_depth;    // path length (edges from u) of each register's key vertex
   std::vector<int> last_use;     // op index of each register's last use
+  int max_depth = 0;
 };
 
 struct Plan {
@@ -159,6 +150,9 @@ uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptio
 
 // Device colouring (rank order) for one trial, copied to host by original id.
 void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t stream);
+
+void profile_enable(bool on);
+std::vector<std::pair<std::string, std::array<double, 3>>> profile_read();
 
 double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf);
 

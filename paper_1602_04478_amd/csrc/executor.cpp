@@ -13,8 +13,13 @@
 // potential entry and the EdgeJoin pulls over all vertices; the rest run in
 // sparse groups, whose registers keep lists of their live entries.
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "cc_internal.h"
 #include "kernels.h"
@@ -54,7 +59,7 @@ struct DevMem {
 };
 
 struct RegBuf {
-  DevMem val, act, list, cnt;
+  DevMem val, act, vmark, vlist, vcnt;
   int C = 0, s = 0;
   bool owns_act = true;
   int alias = -1;  // shares act/list with this register (NodeJoin output)
@@ -117,6 +122,20 @@ Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &o
     if (B >= 1 || z.T == 1) {
       B = std::max<int64_t>(1, std::min<int64_t>(B, 64));
       if (opt.group_sources > 0) B = std::min<int64_t>(B, opt.group_sources);
+      // one workgroup covers every (source, trial, slot) of a vertex
+      int cmax = 1;
+      for (auto &P : p.programs)
+        for (int s : P.reg_s) cmax = std::max(cmax, (int)slots_pair(p.k, s));
+      for (auto &B2 : p.blocks)
+        if (B2.kind == BK_CYCLE) cmax = std::max(cmax, (int)binom(p.k - 1, B2.size - 1));
+      while (B > 1 && (int64_t)B * z.T * cmax > max_items_per_vertex()) B--;
+      if ((int64_t)B * z.T * cmax > max_items_per_vertex()) {
+        if (z.T > 1) {
+          z.T = std::max(1, z.T / 2);
+          continue;
+        }
+        fail(CC_E_UNSUPPORTED, "signature tables too wide for one workgroup");
+      }
       z.B_dense = (int)B;
       z.B_sparse = (int)B;
       if (tabs + per_vb * n * B > budget) fail(CC_E_NOMEM, "plan does not fit the device memory budget");
@@ -126,7 +145,94 @@ Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &o
   }
 }
 
+// ------------------------------------------------------------------ profiling
+struct ProfStat {
+  uint64_t launches = 0;
+  double seconds = 0, bytes = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfStat> g_prof;
+
+// Records of the launches of one call (events are resolved at its end).
+struct Profiler {
+  bool on = false;
+  hipStream_t st;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+    int ctr;            // counter triple index, or -1
+    double per_scan, per_active, per_entry;
+  };
+  std::vector<Rec> recs;
+  std::vector<uint64_t *> ctrs;
+  int nctr = 0;
+  DevMem ctrmem;
+  explicit Profiler(hipStream_t s) : st(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    on = g_prof_on;
+    if (on) ctrmem.alloc(sizeof(uint64_t) * 3 * 65536);
+  }
+  // returns a zeroed counter triple for an EdgeJoin launch (or null)
+  uint64_t *begin(const char *name, bool counters, double per_scan, double per_active, double per_entry) {
+    if (!on) return nullptr;
+    Rec r;
+    r.name = name;
+    HIP_CHECK(hipEventCreate(&r.a));
+    HIP_CHECK(hipEventCreate(&r.b));
+    HIP_CHECK(hipEventRecord(r.a, st));
+    r.ctr = -1;
+    uint64_t *c = nullptr;
+    if (counters && nctr < 65536) {
+      r.ctr = nctr++;
+      c = ctrmem.as<uint64_t>() + 3 * r.ctr;
+      launch_fill_u64(c, 3, st);
+    }
+    r.per_scan = per_scan;
+    r.per_active = per_active;
+    r.per_entry = per_entry;
+    recs.push_back(r);
+    return c;
+  }
+  void end() {
+    if (!on) return;
+    HIP_CHECK(hipEventRecord(recs.back().b, st));
+  }
+  void finish() {
+    if (!on) return;
+    HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<uint64_t> h(3 * (size_t)std::max(1, nctr));
+    if (nctr) HIP_CHECK(hipMemcpy(h.data(), ctrmem.p, sizeof(uint64_t) * 3 * nctr, hipMemcpyDeviceToHost));
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : recs) {
+      float ms = 0;
+      HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      ProfStat &p = g_prof[r.name];
+      p.launches++;
+      p.seconds += ms * 1e-3;
+      if (r.ctr >= 0)
+        p.bytes += h[3 * r.ctr] * r.per_scan + h[3 * r.ctr + 1] * r.per_active + h[3 * r.ctr + 2] * r.per_entry;
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    recs.clear();
+  }
+};
+
 }  // namespace
+
+void profile_enable(bool on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on;
+}
+
+std::vector<std::pair<std::string, std::array<double, 3>>> profile_read() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<std::pair<std::string, std::array<double, 3>>> v;
+  for (auto &kv : g_prof) v.push_back({kv.first, {(double)kv.second.launches, kv.second.seconds, kv.second.bytes}});
+  g_prof.clear();
+  return v;
+}
 
 uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt) {
   int T = std::min(std::max(trials, 1), 64);
@@ -201,18 +307,23 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
   int64_t ndense = 0;
   for (size_t i = 0; i < sources.size(); i++) {
     int64_t u = sources[i];
-    if (g.h_r2[u] * 4 >= u && u > 4096) ndense = (int64_t)i + 1;
+    if (g.h_r2[u] * 16 >= u && u > 4096) ndense = (int64_t)i + 1;
     else break;
   }
-  // groups
-  struct Grp {
-    int64_t lo, hi;
-    bool dense;
-  };
-  std::vector<Grp> groups;
-  for (int64_t i = 0; i < ndense; i += z.B_dense) groups.push_back({i, std::min<int64_t>(ndense, i + z.B_dense), true});
-  for (int64_t i = ndense; i < (int64_t)sources.size(); i += z.B_sparse)
-    groups.push_back({i, std::min<int64_t>((int64_t)sources.size(), i + z.B_sparse), false});
+  // CC_DENSE=all / none overrides the choice (used to exercise both paths)
+  bool force_sparse = false;
+  if (const char *ev = getenv("CC_DENSE")) {
+    if (!strcmp(ev, "all")) ndense = (int64_t)sources.size();
+    if (!strcmp(ev, "none")) {
+      ndense = 0;
+      force_sparse = true;
+    }
+  }
+  bool use_light = true;
+  if (const char *ev = getenv("CC_LIGHT"))
+    if (!strcmp(ev, "0")) use_light = false;
+  int64_t light_scratch = 2 << 20;
+  if (const char *ev = getenv("CC_LIGHT_SCRATCH")) light_scratch = std::max<int64_t>(4096, atoll(ev));
   int Bmax = std::max(z.B_dense, z.B_sparse);
   int64_t nlim_max = sources.empty() ? 1 : sources[0];
   if (nlim_max < 1) nlim_max = 1;
@@ -258,16 +369,24 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
       R.act.alloc(ab);
       launch_fill_u8(R.act.as<uint8_t>(), (int64_t)ab, st);
     }
-    if (R.list.bytes < sizeof(int64_t) * (size_t)nlim_max * Bmax) R.list.alloc(sizeof(int64_t) * (size_t)nlim_max * Bmax);
-    if (!R.cnt.p) {
-      R.cnt.alloc(sizeof(uint32_t));
-      HIP_CHECK(hipMemsetAsync(R.cnt.p, 0, sizeof(uint32_t), st));
+    size_t mb = ((size_t)nlim_max + 3) & ~(size_t)3;
+    if (R.vmark.bytes < mb) {
+      R.vmark.alloc(mb);
+      launch_fill_u8(R.vmark.as<uint8_t>(), (int64_t)mb, st);
+    }
+    if (R.vlist.bytes < sizeof(int32_t) * (size_t)nlim_max) R.vlist.alloc(sizeof(int32_t) * (size_t)nlim_max);
+    if (!R.vcnt.p) {
+      R.vcnt.alloc(sizeof(uint32_t));
+      HIP_CHECK(hipMemsetAsync(R.vcnt.p, 0, sizeof(uint32_t), st));
     }
     R.C = C;
     R.s = s;
   };
 
   const int32_t *lowcnt_d = g.lowcnt;
+  Profiler prof(st);
+  DevMem light_scratch_buf;
+  int64_t light_handled = 0;
 
   for (int t0 = 0; t0 < trials; t0 += T) {
     int Tg = std::min(T, trials - t0);
@@ -322,23 +441,31 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
         int own = alias[r] >= 0 ? alias[r] : r;
         d.val = regs[r].val.as<uint64_t>();
         d.act = regs[own].act.as<uint8_t>();
-        d.list = regs[own].list.as<int64_t>();
-        d.cnt = regs[own].cnt.as<uint32_t>();
+        d.vmark = regs[own].vmark.as<uint8_t>();
+        d.vlist = regs[own].vlist.as<int32_t>();
+        d.vcnt = regs[own].vcnt.as<uint32_t>();
         d.C = (int)slots_pair(k, P.reg_s[r]);
         d.s = P.reg_s[r];
         return d;
       };
       bool prev_dense = false;
-      for (auto &G : groups) {
+      struct Grp {
+        const int32_t *dsrc;          // device sources of the group
+        const int32_t *hsrc;          // host copy
+        int64_t B;
+        bool dense;
+      };
+      auto run_group = [&](const Grp &G) {
         GroupDev grp;
-        grp.src = d_src.as<int32_t>() + G.lo;
-        grp.B = (int)(G.hi - G.lo);
+        grp.src = G.dsrc;
+        grp.B = (int)G.B;
         grp.T = Tg;
         grp.k = k;
-        grp.n_lim = sources[G.lo];
+        grp.n_lim = G.hsrc[0];
         grp.dense = G.dense ? 1 : 0;
+        grp.prof = nullptr;
         int max_low = 0;
-        for (int64_t i = G.lo; i < G.hi; i++) max_low = std::max(max_low, g.h_lowcnt[sources[i]]);
+        for (int64_t i = 0; i < G.B; i++) max_low = std::max(max_low, g.h_lowcnt[G.hsrc[i]]);
         if (!G.dense && prev_dense) {
           // activity bytes hold dense-mode leftovers: clear them all
           for (size_t r = 0; r < P.reg_s.size(); r++)
@@ -347,6 +474,25 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
         prev_dense = G.dense;
         for (size_t oi = 0; oi < P.ops.size(); oi++) {
           const Op &op = P.ops[oi];
+          static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
+                                        "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
+          std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
+          if (op.kind == OP_EJ) {
+            int Cin = (int)slots_pair(k, P.reg_s[op.a]), Cout = (int)slots_pair(k, op.s);
+            if (!G.dense) {
+              prof.begin("edgejoin_mark_sparse", false, 0, 0, 0);
+              launch_mark(gd, grp, regdev(op.a), regdev(op.dst), st);
+              HIP_CHECK(hipGetLastError());
+              prof.end();
+            }
+            grp.prof = prof.begin(nm.c_str(), true, 5.0, 8.0 * Cin * Tg, 8.0 * Cout * Tg);
+            launch_ej(gd, grp, colr, regdev(op.a), regdev(op.dst), tabdev(op.tab), op.tab_src_first, ovf, st);
+            HIP_CHECK(hipGetLastError());
+            prof.end();
+            grp.prof = nullptr;
+            continue;
+          }
+          prof.begin(nm.c_str(), false, 0, 0, 0);
           switch (op.kind) {
             case OP_INIT: {
               RegDev d = regdev(op.dst);
@@ -358,12 +504,8 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
             case OP_NJ:
               launch_nj(gd, grp, colr, regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
               break;
-            case OP_EJ: {
-              RegDev a = regdev(op.a), d = regdev(op.dst);
-              if (!G.dense) launch_mark(gd, grp, a, d, st);
-              launch_ej(gd, grp, colr, a, d, tabdev(op.tab), op.tab_src_first, ovf, st);
+            case OP_EJ:
               break;
-            }
             case OP_AXPY:
               launch_axpy(grp, regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
               break;
@@ -386,11 +528,96 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
               break;
           }
           HIP_CHECK(hipGetLastError());
+          prof.end();
         }
         if (!G.dense) {
           for (size_t r = 0; r < P.reg_s.size(); r++)
             if (alias[r] < 0) launch_clear_list(regdev((int)r), grp.B, st);
         }
+      };
+      // 1. dense groups: the sources with the widest reach
+      for (int64_t i = 0; i < ndense; i += z.B_dense)
+        run_group({d_src.as<int32_t>() + i, sources.data() + i, std::min<int64_t>(z.B_dense, ndense - i), true});
+      // 2. one workgroup per source for the rest; 3. grouped sparse path for what does not fit
+      std::vector<int32_t> rest(sources.begin() + ndense, sources.end());
+      const int64_t nrest = (int64_t)rest.size();
+      bool light_ok = use_light && nrest > 0 && P.max_depth <= light_max_depth() &&
+                      (int)P.reg_s.size() <= light_max_regs();
+      if (light_ok) {
+        std::vector<LOp> lops;
+        for (auto &o : P.ops)
+          lops.push_back({(int)o.kind, o.dst, o.a, o.b, o.tab, o.tab_src_first, o.ntab, o.s, o.first, o.swapped,
+                          o.w});
+        std::vector<int32_t> rd(P.reg_s.size()), rC(P.reg_s.size()), rs(P.reg_s.size());
+        for (size_t r = 0; r < P.reg_s.size(); r++) {
+          rd[r] = P.reg_depth[r];
+          rC[r] = (int32_t)slots_pair(k, P.reg_s[r]);
+          rs[r] = P.reg_s[r];
+        }
+        std::vector<TabDev> tv(p.blocks.size());
+        for (size_t b2 = 0; b2 < p.blocks.size(); b2++) tv[b2] = tabdev(tabs[b2].p ? (int)b2 : -1);
+        DevMem d_ops(sizeof(LOp) * lops.size()), d_rd(4 * rd.size()), d_rC(4 * rC.size()), d_rs(4 * rs.size());
+        DevMem d_tv(sizeof(TabDev) * tv.size()), d_ctr(8), d_fail(4 * nrest);
+        HIP_CHECK(hipMemcpyAsync(d_ops.p, lops.data(), sizeof(LOp) * lops.size(), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(d_rd.p, rd.data(), 4 * rd.size(), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(d_rC.p, rC.data(), 4 * rC.size(), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(d_rs.p, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(d_tv.p, tv.data(), sizeof(TabDev) * tv.size(), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemsetAsync(d_ctr.p, 0, 8, st));
+        int ncu = 0;
+        HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g.device));
+        int grid = std::max(1, ncu) * 3;
+        if (light_scratch_buf.bytes < (size_t)light_scratch * grid) light_scratch_buf.alloc((size_t)light_scratch * grid);
+        DevMem d_rest(4 * nrest);
+        HIP_CHECK(hipMemcpyAsync(d_rest.p, rest.data(), 4 * nrest, hipMemcpyHostToDevice, st));
+        LightArgs la;
+        la.g = gd;
+        la.lowcnt = lowcnt_d;
+        la.colr = colr;
+        la.T = Tg;
+        la.k = k;
+        la.src = d_rest.as<int32_t>();
+        la.nsrc = (int)nrest;
+        la.next = d_ctr.as<uint32_t>();
+        la.fail = d_fail.as<int32_t>();
+        la.nfail = d_ctr.as<uint32_t>() + 1;
+        la.ops = d_ops.as<LOp>();
+        la.nops = (int)lops.size();
+        la.reg_depth = d_rd.as<int32_t>();
+        la.reg_C = d_rC.as<int32_t>();
+        la.reg_s = d_rs.as<int32_t>();
+        la.nregs = (int)rd.size();
+        la.D = P.max_depth;
+        la.tabs = d_tv.as<TabDev>();
+        la.out = out;
+        la.s_out = B.size;
+        la.C_out = C_out;
+        la.acc = acc;
+        la.scratch = light_scratch_buf.as<uint8_t>();
+        la.scratch_per_wg = light_scratch;
+        la.lut = lut_device(g.device);
+        prof.begin("light", false, 0, 0, 0);
+        launch_light(la, grid, st);
+        HIP_CHECK(hipGetLastError());
+        prof.end();
+        uint32_t hc[2];
+        HIP_CHECK(hipMemcpyAsync(hc, d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        rest.resize(hc[1]);
+        if (hc[1]) HIP_CHECK(hipMemcpy(rest.data(), d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost));
+        std::sort(rest.begin(), rest.end(), std::greater<int32_t>());
+        light_handled += nrest - (int64_t)hc[1];
+      }
+      if (!rest.empty()) {
+        DevMem d_f(4 * rest.size());
+        HIP_CHECK(hipMemcpyAsync(d_f.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
+        // what the one-workgroup path handed back has wide reach: dense groups,
+        // unless every path is forced sparse
+        const bool fdense = light_ok && !force_sparse;
+        for (int64_t i = 0; i < (int64_t)rest.size(); i += z.B_sparse)
+          run_group({d_f.as<int32_t>() + i, rest.data() + i, std::min<int64_t>(z.B_sparse, (int64_t)rest.size() - i),
+                     fdense});
+        HIP_CHECK(hipStreamSynchronize(st));
       }
       if (prev_dense) {
         for (size_t r = 0; r < P.reg_s.size(); r++)
@@ -408,6 +635,7 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
       HIP_CHECK(hipMemcpyAsync(hp.data(), d_per.p, sizeof(uint64_t) * hp.size(), hipMemcpyDeviceToHost, st));
     }
     HIP_CHECK(hipStreamSynchronize(st));
+    prof.finish();
     for (int t = 0; t < Tg; t++) {
       res.exact[t0 + t] = (u128)hs[2 * t] | ((u128)hs[2 * t + 1] << 64);
       res.overflow[t0 + t] = ho[t] ? 1 : 0;

@@ -8,14 +8,29 @@
 
 namespace cc {
 
+// Frontier program operations (see planner.cpp).
+enum OpKind {
+  OP_INIT = 0,   // dst[x] = A_h[u] (x) E(u,x), x a lower neighbour of u
+  OP_NJ = 1,     // dst[v] = a[v] (x) A[v]                      (NodeJoin)
+  OP_EJ = 2,     // dst[w] = sum_{v in N(w), v < u} a[v] (x) E(v,w)   (EdgeJoin)
+  OP_AXPY = 3,   // dst += w * a   (dst fresh on its first AXPY)
+  OP_MROOT = 4,  // count += w * sum_v a[v] (x) b[v], signatures covering all k colours
+  OP_MU = 5,     // U[u]  += w * sum_v a[v] (x) b[v]
+  OP_MV = 6,     // U[v]  += w * a[v] (x) b[v]
+  OP_MEDGE = 7,  // T[x,y] += w * a[x] (x) E(x,y) (x) b[y]
+  OP_MEDGE_T = 8 // T[u,y] += w * A[u] (x) E(u,y) (x) b[y]   (or T[y,u] when swapped)
+};
+
 // A frontier register for one group of B sources and T colourings: values
-// [v][b][t][slot] for v in [0, n_lim), activity bytes [v][b], and (sparse
-// mode) a list of active (v, b) entries encoded v*64 + b with its length.
+// [v][b][t][slot] for v in [0, n_lim) and activity bytes [v][b].  In sparse
+// mode the register also lists the distinct vertices holding an entry for
+// some source (vmark[v] = 1 once v is listed).
 struct RegDev {
   uint64_t *val;
   uint8_t *act;
-  int64_t *list;
-  uint32_t *cnt;
+  uint8_t *vmark;
+  int32_t *vlist;
+  uint32_t *vcnt;
   int C;  // slots per (v, b, t)
   int s;  // signature size
 };
@@ -28,6 +43,7 @@ struct GroupDev {
   int k;
   int64_t n_lim;      // every frontier vertex is below this rank
   int dense;          // 1: domain = all (v, b) with v < n_lim; 0: the register's list
+  uint64_t *prof;     // optional counters: [edges scanned, active in-neighbours, entries written]
 };
 
 struct GraphDev {
@@ -52,7 +68,8 @@ struct AccDev {
   uint64_t *per_src;   // optional [n][T] x (lo, hi) by rank, or null
 };
 
-const uint16_t *lut_device(int device);  // colex rank / unrank tables
+const uint16_t *lut_device(int device);
+int max_items_per_vertex();  // (source, trial, slot) items one workgroup covers  // colex rank / unrank tables
 
 void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0, int T, uint8_t *out,
                    hipStream_t st);
@@ -86,5 +103,38 @@ void launch_medge_t(const GraphDev &g, const GroupDev &grp, const uint8_t *colr,
 void launch_leaf(const GraphDev &g, int T, int k, const uint8_t *colr, TabDev na, TabDev ea, int e_src_first,
                  TabDev nb, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
 void launch_root_single(int64_t n, int T, TabDev u, AccDev acc, hipStream_t st);
+
+// ------------------------------------------------------------------ one workgroup per source
+struct LOp {
+  int kind, dst, a, b, tab, tab_src_first, ntab, s, first, swapped;
+  uint64_t w;
+};
+
+struct LightArgs {
+  GraphDev g;
+  const int32_t *lowcnt;
+  const uint8_t *colr;
+  int T, k;
+  const int32_t *src;   // candidate sources (ranks)
+  int nsrc;
+  uint32_t *next;       // work counter (zero before launch)
+  int32_t *fail;        // sources handed back
+  uint32_t *nfail;
+  const LOp *ops;
+  int nops;
+  const int32_t *reg_depth, *reg_C, *reg_s;
+  int nregs, D;
+  const TabDev *tabs;   // per block id (null val: no table)
+  uint64_t *out;        // the block's output table (non-root)
+  int s_out, C_out;
+  AccDev acc;
+  uint8_t *scratch;
+  int64_t scratch_per_wg;
+  const uint16_t *lut;
+};
+
+int light_max_depth();
+int light_max_regs();
+void launch_light(const LightArgs &a, int grid, hipStream_t st);
 
 }  // namespace cc

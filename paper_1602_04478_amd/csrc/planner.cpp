@@ -628,8 +628,15 @@ static Program build_program(const Plan &plan, int bi) {
     op.first = swapped ? !first_is_lo : first_is_lo;
     pb.prog.ops.push_back(op);
   }
-  // register lifetimes
+  // register lifetimes and depths
   Program &P = pb.prog;
+  P.reg_depth.assign(P.reg_s.size(), 0);
+  for (auto &o : P.ops) {
+    if (o.kind == OP_INIT) P.reg_depth[o.dst] = 1;
+    else if (o.kind == OP_EJ) P.reg_depth[o.dst] = P.reg_depth[o.a] + 1;
+    else if (o.kind == OP_NJ || o.kind == OP_AXPY) P.reg_depth[o.dst] = P.reg_depth[o.a];
+  }
+  for (int d : P.reg_depth) P.max_depth = std::max(P.max_depth, d);
   P.last_use.assign(P.reg_s.size(), -1);
   for (int i = 0; i < (int)P.ops.size(); i++) {
     const Op &o = P.ops[i];

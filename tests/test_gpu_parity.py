@@ -34,12 +34,32 @@ def small_graphs():
             graphs.erdos_renyi(25, 12.0, seed=23)]
 
 
+PATH_MODES = {
+    "auto": {},
+    "dense": {"CC_DENSE": "all"},
+    "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
+    "light": {"CC_DENSE": "none"},
+    "light+fallback": {"CC_DENSE": "none", "CC_LIGHT_SCRATCH": "6000"},
+    "light+densefallback": {"CC_LIGHT_SCRATCH": "6000"},
+}
+
+
+@pytest.fixture(params=sorted(PATH_MODES))
+def dense_mode(request, monkeypatch):
+    """Which execution path the sources take: the library's choice, all in
+    dense groups, all in sparse groups, one workgroup per source, or one
+    workgroup per source with a scratch so small that many are handed back."""
+    for k, v in PATH_MODES[request.param].items():
+        monkeypatch.setenv(k, v)
+    return request.param
+
+
 @pytest.mark.parametrize("name", sorted(SHAPES))
-def test_small_shapes_match_oracle(small_graphs, name):
+def test_small_shapes_match_oracle(small_graphs, name, dense_mode):
     k, E = SHAPES[name]
     q = cc.Query(k, E)
     for gi, g in enumerate(small_graphs):
-        print(f"[parity] {name} graph{gi} n={g.n} m={g.m}", flush=True)
+        print(f"[parity] {name} graph{gi} n={g.n} m={g.m} mode={dense_mode}", flush=True)
         dg = cc.Graph.from_csr(g)
         col = _colours(g.n, k, 3, seed=100 + gi)
         counts, ovf, exact = cc.count_colors(dg, q, col)
