@@ -59,10 +59,10 @@ struct DevMem {
 };
 
 struct RegBuf {
-  DevMem val, act, vmark, vlist, vcnt;
-  int C = 0, s = 0;
-  bool owns_act = true;
-  int alias = -1;  // shares act/list with this register (NodeJoin output)
+  DevMem val;
+};
+struct LevelBuf {
+  DevMem idx, list, cnt, flag;
 };
 
 int table_C(const Plan &p, int blk) {
@@ -128,8 +128,7 @@ Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &o
         for (int s : P.reg_s) cmax = std::max(cmax, (int)slots_pair(p.k, s));
       for (auto &B2 : p.blocks)
         if (B2.kind == BK_CYCLE) cmax = std::max(cmax, (int)binom(p.k - 1, B2.size - 1));
-      while (B > 1 && (int64_t)B * z.T * cmax > max_items_per_vertex()) B--;
-      if ((int64_t)B * z.T * cmax > max_items_per_vertex()) {
+      if ((int64_t)z.T * cmax > max_row_slots()) {
         if (z.T > 1) {
           z.T = std::max(1, z.T / 2);
           continue;
@@ -355,32 +354,40 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
     return t;
   };
 
-  // registers: one pool sized for the largest program
+  // registers and levels: pools sized for the largest program
   size_t nregs = 0;
-  for (auto &P : p.programs) nregs = std::max(nregs, P.reg_s.size());
+  int dmax = 1;
+  for (auto &P : p.programs) {
+    nregs = std::max(nregs, P.reg_s.size());
+    dmax = std::max(dmax, P.max_depth);
+  }
   std::vector<RegBuf> regs(nregs);
   auto ensure_reg = [&](int r, int s) {
     RegBuf &R = regs[r];
     int C = (int)slots_pair(k, s);
     size_t vb = sizeof(uint64_t) * (size_t)nlim_max * Bmax * T * C;
     if (R.val.bytes < vb) R.val.alloc(vb);
-    size_t ab = ((size_t)nlim_max * Bmax + 3) & ~(size_t)3;
-    if (R.act.bytes < ab) {
-      R.act.alloc(ab);
-      launch_fill_u8(R.act.as<uint8_t>(), (int64_t)ab, st);
-    }
-    size_t mb = ((size_t)nlim_max + 3) & ~(size_t)3;
-    if (R.vmark.bytes < mb) {
-      R.vmark.alloc(mb);
-      launch_fill_u8(R.vmark.as<uint8_t>(), (int64_t)mb, st);
-    }
-    if (R.vlist.bytes < sizeof(int32_t) * (size_t)nlim_max) R.vlist.alloc(sizeof(int32_t) * (size_t)nlim_max);
-    if (!R.vcnt.p) {
-      R.vcnt.alloc(sizeof(uint32_t));
-      HIP_CHECK(hipMemsetAsync(R.vcnt.p, 0, sizeof(uint32_t), st));
-    }
-    R.C = C;
-    R.s = s;
+  };
+  std::vector<LevelBuf> levels(dmax + 2);
+  const size_t nf_max = (size_t)nlim_max * Bmax;
+  auto ensure_level = [&](int d) {
+    LevelBuf &L = levels[d];
+    if (L.flag.bytes >= nf_max) return;
+    L.flag.alloc(nf_max);
+    launch_fill_u8(L.flag.as<uint8_t>(), (int64_t)nf_max, st);
+    L.idx.alloc(sizeof(int32_t) * nf_max);
+    launch_fill_u8(L.idx.as<uint8_t>(), (int64_t)(sizeof(int32_t) * nf_max), st, 0xff);
+    L.list.alloc(sizeof(int64_t) * (nf_max + nf_max / 4096 + 64));
+    L.cnt.alloc(sizeof(uint32_t));
+    HIP_CHECK(hipMemsetAsync(L.cnt.p, 0, sizeof(uint32_t), st));
+  };
+  auto leveldev = [&](int d) {
+    LevelDev L;
+    L.idx = levels[d].idx.as<int32_t>();
+    L.list = levels[d].list.as<int64_t>();
+    L.cnt = levels[d].cnt.as<uint32_t>();
+    L.flag = levels[d].flag.as<uint8_t>();
+    return L;
   };
 
   const int32_t *lowcnt_d = g.lowcnt;
@@ -432,23 +439,15 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
         launch_fill_u64(out, keys * Tg * C_out, st);
       }
       for (size_t r = 0; r < P.reg_s.size(); r++) ensure_reg((int)r, P.reg_s[r]);
-      // registers whose activity/list belong to another (NodeJoin outputs)
-      std::vector<int> alias(P.reg_s.size(), -1);
-      for (auto &op : P.ops)
-        if (op.kind == OP_NJ) alias[op.dst] = alias[op.a] >= 0 ? alias[op.a] : op.a;
+      for (int d = 1; d <= P.max_depth; d++) ensure_level(d);
       auto regdev = [&](int r) {
         RegDev d;
-        int own = alias[r] >= 0 ? alias[r] : r;
         d.val = regs[r].val.as<uint64_t>();
-        d.act = regs[own].act.as<uint8_t>();
-        d.vmark = regs[own].vmark.as<uint8_t>();
-        d.vlist = regs[own].vlist.as<int32_t>();
-        d.vcnt = regs[own].vcnt.as<uint32_t>();
         d.C = (int)slots_pair(k, P.reg_s[r]);
         d.s = P.reg_s[r];
         return d;
       };
-      bool prev_dense = false;
+      auto lv = [&](int r) { return leveldev(P.reg_depth[r]); };
       struct Grp {
         const int32_t *dsrc;          // device sources of the group
         const int32_t *hsrc;          // host copy
@@ -466,74 +465,69 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
         grp.prof = nullptr;
         int max_low = 0;
         for (int64_t i = 0; i < G.B; i++) max_low = std::max(max_low, g.h_lowcnt[G.hsrc[i]]);
-        if (!G.dense && prev_dense) {
-          // activity bytes hold dense-mode leftovers: clear them all
-          for (size_t r = 0; r < P.reg_s.size(); r++)
-            if (alias[r] < 0) launch_fill_u8(regs[r].act.as<uint8_t>(), (int64_t)regs[r].act.bytes, st);
-        }
-        prev_dense = G.dense;
+        std::vector<char> built(P.max_depth + 2, 0);
+        std::function<void(int)> build = [&](int d) {  // sparse groups: entries of depth d
+          if (G.dense || built[d]) return;
+          prof.begin("level_build_sparse", false, 0, 0, 0);
+          if (d == 1) {
+            launch_level_init(gd, grp, lowcnt_d, max_low, leveldev(1), st);
+            launch_level_compact(grp, leveldev(1), st);
+          } else {
+            build(d - 1);
+            launch_level_next(gd, grp, leveldev(d - 1), leveldev(d), st);
+          }
+          HIP_CHECK(hipGetLastError());
+          prof.end();
+          built[d] = 1;
+        };
         for (size_t oi = 0; oi < P.ops.size(); oi++) {
           const Op &op = P.ops[oi];
           static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
                                         "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
           std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
-          if (op.kind == OP_EJ) {
-            int Cin = (int)slots_pair(k, P.reg_s[op.a]), Cout = (int)slots_pair(k, op.s);
-            if (!G.dense) {
-              prof.begin("edgejoin_mark_sparse", false, 0, 0, 0);
-              launch_mark(gd, grp, regdev(op.a), regdev(op.dst), st);
-              HIP_CHECK(hipGetLastError());
-              prof.end();
-            }
-            grp.prof = prof.begin(nm.c_str(), true, 5.0, 8.0 * Cin * Tg, 8.0 * Cout * Tg);
-            launch_ej(gd, grp, colr, regdev(op.a), regdev(op.dst), tabdev(op.tab), op.tab_src_first, ovf, st);
-            HIP_CHECK(hipGetLastError());
-            prof.end();
-            grp.prof = nullptr;
-            continue;
-          }
+          if (op.kind == OP_INIT) build(1);
+          if (op.kind == OP_EJ) build(P.reg_depth[op.dst]);
           prof.begin(nm.c_str(), false, 0, 0, 0);
           switch (op.kind) {
             case OP_INIT: {
               RegDev d = regdev(op.dst);
-              if (G.dense) launch_fill_u8(d.act, grp.n_lim * grp.B, st);
-              launch_init(gd, grp, lowcnt_d, max_low, colr, d, tabdev(op.tab), op.tab_src_first, tabdev(op.ntab),
-                          ovf, st);
+              if (G.dense) launch_fill_u64(d.val, grp.n_lim * grp.B * (int64_t)Tg * d.C, st);
+              launch_init(gd, grp, lowcnt_d, max_low, colr, lv(op.dst), d, tabdev(op.tab), op.tab_src_first,
+                          tabdev(op.ntab), ovf, st);
               break;
             }
             case OP_NJ:
-              launch_nj(gd, grp, colr, regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
+              launch_nj(gd, grp, colr, lv(op.a), regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
               break;
             case OP_EJ:
+              launch_ej(gd, grp, colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst), tabdev(op.tab),
+                        op.tab_src_first, ovf, st);
               break;
             case OP_AXPY:
-              launch_axpy(grp, regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
+              launch_axpy(grp, lv(op.a), regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
               break;
             case OP_MROOT:
-              launch_mroot(grp, g.n, colr, regdev(op.a), regdev(op.b), op.w, acc, st);
+              launch_mroot(grp, g.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w, acc, st);
               break;
             case OP_MU:
-              launch_mu(grp, g.n, colr, regdev(op.a), regdev(op.b), op.w, out, op.s, C_out, ovf, st);
-              break;
             case OP_MV:
-              launch_mv(grp, g.n, colr, regdev(op.a), regdev(op.b), op.w, out, op.s, C_out, ovf, st);
+              launch_munary(grp, g.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w,
+                            op.kind == OP_MU, out, op.s, C_out, ovf, st);
               break;
             case OP_MEDGE:
-              launch_medge(gd, grp, colr, regdev(op.a), regdev(op.b), tabdev(op.tab), op.tab_src_first, op.first,
-                           op.w, out, op.s, C_out, ovf, st);
+              launch_medge(gd, grp, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), tabdev(op.tab),
+                           op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
               break;
             case OP_MEDGE_T:
-              launch_medge_t(gd, grp, colr, lowcnt_d, max_low, tabdev(op.ntab), regdev(op.b), tabdev(op.tab),
-                             op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
+              launch_medge_t(gd, grp, colr, lowcnt_d, max_low, tabdev(op.ntab), lv(op.b), regdev(op.b),
+                             tabdev(op.tab), op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
               break;
           }
           HIP_CHECK(hipGetLastError());
           prof.end();
         }
-        if (!G.dense) {
-          for (size_t r = 0; r < P.reg_s.size(); r++)
-            if (alias[r] < 0) launch_clear_list(regdev((int)r), grp.B, st);
-        }
+        for (int d = 1; d <= P.max_depth; d++)
+          if (built[d]) launch_level_reset(grp, leveldev(d), st);
       };
       // 1. dense groups: the sources with the widest reach
       for (int64_t i = 0; i < ndense; i += z.B_dense)
@@ -613,15 +607,13 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
         HIP_CHECK(hipMemcpyAsync(d_f.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
         // what the one-workgroup path handed back has wide reach: dense groups,
         // unless every path is forced sparse
-        const bool fdense = light_ok && !force_sparse;
+        bool fdense = false;
+        if (const char *ev = getenv("CC_FALLBACK"))
+          if (!strcmp(ev, "dense")) fdense = true;
         for (int64_t i = 0; i < (int64_t)rest.size(); i += z.B_sparse)
           run_group({d_f.as<int32_t>() + i, rest.data() + i, std::min<int64_t>(z.B_sparse, (int64_t)rest.size() - i),
                      fdense});
         HIP_CHECK(hipStreamSynchronize(st));
-      }
-      if (prev_dense) {
-        for (size_t r = 0; r < P.reg_s.size(); r++)
-          if (alias[r] < 0) launch_fill_u8(regs[r].act.as<uint8_t>(), (int64_t)regs[r].act.bytes, st);
       }
     }
     // results of this trial group

@@ -21,17 +21,21 @@ enum OpKind {
   OP_MEDGE_T = 8 // T[u,y] += w * A[u] (x) E(u,y) (x) b[y]   (or T[y,u] when swapped)
 };
 
-// A frontier register for one group of B sources and T colourings: values
-// [v][b][t][slot] for v in [0, n_lim) and activity bytes [v][b].  In sparse
-// mode the register also lists the distinct vertices holding an entry for
-// some source (vmark[v] = 1 once v is listed).
+// The entries of one path length (depth) for a group: the (vertex, source)
+// pairs reachable by a high-starting walk of that length.  In dense mode the
+// entry of (v, b) is v * B + b for every v < n_lim; in sparse mode entries are
+// listed (v * 64 + b) and idx maps (v, b) to its entry or -1.
+struct LevelDev {
+  int32_t *idx;    // [n_lim * B]
+  int64_t *list;   // [entries]
+  uint32_t *cnt;   // number of entries
+  uint8_t *flag;   // [n_lim * B] marks while the level is built
+};
+
+// A frontier register: one row of T * C slots per entry of its level.
 struct RegDev {
   uint64_t *val;
-  uint8_t *act;
-  uint8_t *vmark;
-  int32_t *vlist;
-  uint32_t *vcnt;
-  int C;  // slots per (v, b, t)
+  int C;  // slots per (entry, trial)
   int s;  // signature size
 };
 
@@ -69,37 +73,40 @@ struct AccDev {
 };
 
 const uint16_t *lut_device(int device);
-int max_items_per_vertex();  // (source, trial, slot) items one workgroup covers  // colex rank / unrank tables
+inline int max_row_slots() { return 6144; }  // trials x slots of one frontier row (EdgeJoin LDS)  // colex rank / unrank tables
 
 void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0, int T, uint8_t *out,
                    hipStream_t st);
 void launch_permute_colours(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out,
                             hipStream_t st);
-void launch_fill_u8(uint8_t *p, int64_t n, hipStream_t st);
+void launch_fill_u8(uint8_t *p, int64_t n, hipStream_t st, uint8_t x = 0);
 void launch_fill_u64(uint64_t *p, int64_t n, hipStream_t st);
-void launch_clear_list(RegDev r, int B, hipStream_t st);
 
+// grouped path (heavy.hip)
+void launch_level_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, LevelDev L,
+                       hipStream_t st);
+void launch_level_next(const GraphDev &g, const GroupDev &grp, LevelDev Lin, LevelDev Lout, hipStream_t st);
+void launch_level_compact(const GroupDev &grp, LevelDev L, hipStream_t st);
+void launch_level_reset(const GroupDev &grp, LevelDev L, hipStream_t st);
 void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, const uint8_t *colr,
-                 RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st);
-void launch_mark(const GraphDev &g, const GroupDev &grp, RegDev a, RegDev dst, hipStream_t st);
-void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, RegDev a, RegDev dst, TabDev etab,
-               int e_src_first, uint32_t *ovf, hipStream_t st);
-void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, RegDev a, RegDev dst, TabDev ntab,
-               uint32_t *ovf, hipStream_t st);
-void launch_axpy(const GroupDev &grp, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,
+                 LevelDev L, RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st);
+void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
+               RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st);
+void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev L, RegDev a, RegDev dst,
+               TabDev ntab, uint32_t *ovf, hipStream_t st);
+void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,
                  hipStream_t st);
-void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w,
-                  AccDev acc, hipStream_t st);
-void launch_mu(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w, uint64_t *out,
-               int s_out, int C_out, uint32_t *ovf, hipStream_t st);
-void launch_mv(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w, uint64_t *out,
-               int s_out, int C_out, uint32_t *ovf, hipStream_t st);
-void launch_medge(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, RegDev a, RegDev b, TabDev etab,
-                  int e_src_first, int out_first_is_x, uint64_t w, uint64_t *out, int s_out, int C_out,
-                  uint32_t *ovf, hipStream_t st);
+void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,
+                  uint64_t w, AccDev acc, hipStream_t st);
+void launch_munary(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,
+                   RegDev b, uint64_t w, int at_u, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
+void launch_medge(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,
+                  RegDev b, TabDev etab, int e_src_first, int out_first_is_x, uint64_t w, uint64_t *out, int s_out,
+                  int C_out, uint32_t *ovf, hipStream_t st);
 void launch_medge_t(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, const int32_t *lowcnt,
-                    int max_low, TabDev ntab, RegDev b, TabDev etab, int e_src_first, int out_first_is_u,
-                    uint64_t w, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
+                    int max_low, TabDev ntab, LevelDev Lb, RegDev b, TabDev etab, int e_src_first,
+                    int out_first_is_u, uint64_t w, uint64_t *out, int s_out, int C_out, uint32_t *ovf,
+                    hipStream_t st);
 void launch_leaf(const GraphDev &g, int T, int k, const uint8_t *colr, TabDev na, TabDev ea, int e_src_first,
                  TabDev nb, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
 void launch_root_single(int64_t n, int T, TabDev u, AccDev acc, hipStream_t st);

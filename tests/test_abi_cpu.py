@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/cc.h declares, and the planner behaves."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from cc_inputs import queries as Q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "cc.h")).read()
+    return sorted(set(re.findall(r"^(?:cc_status|const char \*)\s*(cc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1602_04478_amd import cc
+    L = cc.lib()
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(cc.EXPORTS) == names
+
+
+def test_status_strings():
+    from paper_1602_04478_amd import cc
+    for st in range(10):
+        assert cc.lib().cc_status_str(st)
+
+
+@pytest.mark.parametrize("shape,aut", [(Q.cycle(5), 10), (Q.cycle(6), 12), (Q.cycle_pendant(6), 2),
+                                       (Q.star(5), 24), (Q.path(4), 2), (Q.domino_tail(), 1)])
+def test_aut(shape, aut):
+    from paper_1602_04478_amd import cc
+    k, E = shape
+    assert cc.Query(k, E).info()["aut"] == aut
+
+
+def test_aut_complete_like():
+    from paper_1602_04478_amd import cc
+    # C_k: 2k ; K4 minus an edge (diamond, treewidth 2): 4
+    for L in range(3, 11):
+        assert cc.Query(*Q.cycle(L)).info()["aut"] == 2 * L
+    assert cc.Query(4, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)]).info()["aut"] == 4
+
+
+def test_planner_rejects():
+    from paper_1602_04478_amd import cc
+    with pytest.raises(cc.CCError) as e:
+        cc.Query(*Q.k4())
+    assert e.value.name == "CC_E_QUERY_TW"
+    with pytest.raises(cc.CCError) as e:
+        cc.Query(4, [(0, 1), (2, 3)])
+    assert e.value.name == "CC_E_QUERY_DISCONNECTED"
+    with pytest.raises(cc.CCError) as e:
+        cc.Query(13, Q.cycle(13)[1])
+    assert e.value.name == "CC_E_K_RANGE"
+    with pytest.raises(cc.CCError) as e:
+        cc.Query(3, [(0, 1), (1, 1)])
+    assert e.value.name == "CC_E_ARG"
+    with pytest.raises(cc.CCError) as e:
+        cc.Query(*Q.k23())   # every tree needs a pair-keyed table
+    assert e.value.name == "CC_E_UNSUPPORTED"
+
+
+def test_planner_trees():
+    from paper_1602_04478_amd import cc
+    p = cc.Query(*Q.cycle_pendant(6)).plan()
+    assert [b["kind"] for b in p] == ["leaf", "root_cycle"]
+    assert p[1]["children"] == [0] and p[1]["size"] == 7
+    p = cc.Query(*Q.domino_tail()).plan()
+    kinds = [b["kind"] for b in p]
+    assert kinds.count("leaf") == 2 and kinds[-1] == "root_cycle"
+    two = [b for b in p if b["kind"] == "cycle"]
+    assert len(two) == 1 and len(two[0]["boundary"]) == 2
+    # the two boundary nodes of an edge-keyed block are adjacent in its cycle
+    c = two[0]["nodes"]
+    i, j = c.index(two[0]["boundary"][0]), c.index(two[0]["boundary"][1])
+    assert (i - j) % len(c) in (1, len(c) - 1)
+    # sizes of subqueries add up
+    assert p[-1]["size"] == 8
+    # a tree query ends in a singleton root
+    assert cc.Query(*Q.star(5)).plan()[-1]["kind"] == "root_single"
+
+
+def test_planner_heuristic_prefers_short_cycles():
+    """Section 5: the longest cycle block is the first criterion."""
+    from paper_1602_04478_amd import cc
+    # C_8 with chord (0,4): two 5-cycles, never the 8-cycle
+    info = cc.Query(8, Q.cycle(8)[1] + [(0, 4)]).info()
+    assert info["longest_cycle"] == 5
+    # random generated queries all plan (edge-keyed tables suffice)
+    rng = np.random.default_rng(0)
+    for _ in range(60):
+        k, E, fam = Q.random_query(rng, 4, 10)
+        q = cc.Query(k, E)
+        assert q.info()["num_blocks"] >= 1

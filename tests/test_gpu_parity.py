@@ -40,7 +40,7 @@ PATH_MODES = {
     "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
     "light": {"CC_DENSE": "none"},
     "light+fallback": {"CC_DENSE": "none", "CC_LIGHT_SCRATCH": "6000"},
-    "light+densefallback": {"CC_LIGHT_SCRATCH": "6000"},
+    "light+densefallback": {"CC_LIGHT_SCRATCH": "6000", "CC_FALLBACK": "dense"},
 }
 
 
