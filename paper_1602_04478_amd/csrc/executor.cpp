@@ -59,10 +59,10 @@ struct DevMem {
 };
 
 struct RegBuf {
-  DevMem val;
+  DevMem val, mask;
 };
 struct LevelBuf {
-  DevMem idx, list, cnt, flag;
+  DevMem idx, list, cnt, flag, vflag;
 };
 
 int table_C(const Plan &p, int blk) {
@@ -367,6 +367,7 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
     int C = (int)slots_pair(k, s);
     size_t vb = sizeof(uint64_t) * (size_t)nlim_max * Bmax * T * C;
     if (R.val.bytes < vb) R.val.alloc(vb);
+    if (R.mask.bytes < sizeof(uint64_t) * (size_t)nlim_max) R.mask.alloc(sizeof(uint64_t) * (size_t)nlim_max);
   };
   std::vector<LevelBuf> levels(dmax + 2);
   const size_t nf_max = (size_t)nlim_max * Bmax;
@@ -375,6 +376,8 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
     if (L.flag.bytes >= nf_max) return;
     L.flag.alloc(nf_max);
     launch_fill_u8(L.flag.as<uint8_t>(), (int64_t)nf_max, st);
+    L.vflag.alloc(nlim_max);
+    launch_fill_u8(L.vflag.as<uint8_t>(), (int64_t)nlim_max, st);
     L.idx.alloc(sizeof(int32_t) * nf_max);
     launch_fill_u8(L.idx.as<uint8_t>(), (int64_t)(sizeof(int32_t) * nf_max), st, 0xff);
     L.list.alloc(sizeof(int64_t) * (nf_max + nf_max / 4096 + 64));
@@ -387,6 +390,7 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
     L.list = levels[d].list.as<int64_t>();
     L.cnt = levels[d].cnt.as<uint32_t>();
     L.flag = levels[d].flag.as<uint8_t>();
+    L.vflag = levels[d].vflag.as<uint8_t>();
     return L;
   };
 
@@ -440,9 +444,15 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
       }
       for (size_t r = 0; r < P.reg_s.size(); r++) ensure_reg((int)r, P.reg_s[r]);
       for (int d = 1; d <= P.max_depth; d++) ensure_level(d);
+      // NodeJoin outputs keep their input's activity mask
+      std::vector<int> mown(P.reg_s.size());
+      for (size_t r = 0; r < mown.size(); r++) mown[r] = (int)r;
+      for (auto &op : P.ops)
+        if (op.kind == OP_NJ) mown[op.dst] = mown[op.a];
       auto regdev = [&](int r) {
         RegDev d;
         d.val = regs[r].val.as<uint64_t>();
+        d.mask = regs[mown[r]].mask.as<uint64_t>();
         d.C = (int)slots_pair(k, P.reg_s[r]);
         d.s = P.reg_s[r];
         return d;
@@ -491,7 +501,10 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
           switch (op.kind) {
             case OP_INIT: {
               RegDev d = regdev(op.dst);
-              if (G.dense) launch_fill_u64(d.val, grp.n_lim * grp.B * (int64_t)Tg * d.C, st);
+              if (G.dense) {
+                launch_fill_u64(d.val, grp.n_lim * grp.B * (int64_t)Tg * d.C, st);
+                launch_fill_u64(d.mask, grp.n_lim, st);
+              }
               launch_init(gd, grp, lowcnt_d, max_low, colr, lv(op.dst), d, tabdev(op.tab), op.tab_src_first,
                           tabdev(op.ntab), ovf, st);
               break;

@@ -49,6 +49,15 @@ __device__ __forceinline__ int64_t entry_of(const GroupDev &g, const LevelDev &L
   if (g.dense) return v < g.n_lim ? v * g.B + b : -1;
   return L.idx[v * g.B + b];
 }
+// row of register r for (v, b), or -1 when it has none (sparse) or is known
+// to be zero (dense: its activity bit is clear)
+__device__ __forceinline__ int64_t row_of(const GroupDev &g, const LevelDev &L, const RegDev &r, int64_t v, int b) {
+  if (g.dense) return (v < g.n_lim && ((r.mask[v] >> b) & 1ull)) ? v * g.B + b : -1;
+  return L.idx[v * g.B + b];
+}
+__device__ __forceinline__ bool live(const GroupDev &g, const RegDev &r, int64_t v, int b) {
+  return !g.dense || ((r.mask[v] >> b) & 1ull);
+}
 
 // ------------------------------------------------------------------ levels (sparse groups)
 // depth 1: the lower neighbours of each source
@@ -60,6 +69,7 @@ __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int
     if (j >= lowcnt[u]) continue;
     const int64_t x = g.col[g.rp[u] + j];
     L.flag[x * grp.B + b] = 1;
+    L.vflag[x] = 1;
   }
 }
 
@@ -77,17 +87,26 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
       const int64_t w = g.col[ee];
       if (w >= u) break;
       Lout.flag[w * grp.B + b] = 1;
+      Lout.vflag[w] = 1;
     }
   }
 }
 
+// Compaction walks vertices in chunks of CH (32 per thread): only vertices
+// with their per-vertex mark set have their B source marks read.
+__device__ __forceinline__ uint32_t count_marks(const uint8_t *flag, int64_t v, int B) {
+  uint32_t c = 0;
+  for (int b = 0; b < B; b++) c += flag[v * B + b] != 0;
+  return c;
+}
+
 // count marks per chunk
-__global__ void k_cmp_count(const uint8_t *flag, int64_t nf, uint32_t *bcnt) {
+__global__ void k_cmp_count(const uint8_t *flag, const uint8_t *vflag, int64_t nv, int B, uint32_t *bcnt) {
   __shared__ uint32_t s[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH + (int64_t)threadIdx.x * (CH / BLK);
   uint32_t c = 0;
   for (int i = 0; i < CH / BLK; i++)
-    if (lo + i < nf) c += flag[lo + i] != 0;
+    if (lo + i < nv && vflag[lo + i]) c += count_marks(flag, lo + i, B);
   s[threadIdx.x] = c;
   __syncthreads();
   for (int o = BLK / 2; o > 0; o >>= 1) {
@@ -125,14 +144,15 @@ __global__ void k_cmp_scan(uint32_t *bcnt, int nb, uint32_t *cnt) {
   }
 }
 
-// number the marks in order: idx and list, clearing the marks
-__global__ void k_cmp_emit(uint8_t *flag, int64_t nf, const uint32_t *boff, int B, int32_t *idx, int64_t *list) {
-  __shared__ uint32_t s[BLK + 1];
+// number the marks in (vertex, source) order: idx and list, clearing the marks
+__global__ void k_cmp_emit(uint8_t *flag, uint8_t *vflag, int64_t nv, const uint32_t *boff, int B, int32_t *idx,
+                           int64_t *list) {
+  __shared__ uint32_t s[BLK];
   const int per = CH / BLK;
   const int64_t lo = (int64_t)blockIdx.x * CH + (int64_t)threadIdx.x * per;
   uint32_t c = 0;
   for (int i = 0; i < per; i++)
-    if (lo + i < nf) c += flag[lo + i] != 0;
+    if (lo + i < nv && vflag[lo + i]) c += count_marks(flag, lo + i, B);
   s[threadIdx.x] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -146,12 +166,15 @@ __global__ void k_cmp_emit(uint8_t *flag, int64_t nf, const uint32_t *boff, int 
   __syncthreads();
   uint32_t id = boff[blockIdx.x] + s[threadIdx.x];
   for (int i = 0; i < per; i++) {
-    const int64_t f = lo + i;
-    if (f < nf && flag[f]) {
+    const int64_t v = lo + i;
+    if (v >= nv || !vflag[v]) continue;
+    vflag[v] = 0;
+    for (int b = 0; b < B; b++) {
+      const int64_t f = v * B + b;
+      if (!flag[f]) continue;
       flag[f] = 0;
       idx[f] = (int32_t)id;
-      const int64_t v = f / B;
-      list[id] = v * 64 + (f - v * B);
+      list[id] = v * 64 + b;
       id++;
     }
   }
@@ -208,6 +231,7 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
       }
     }
     dst.val[e * per + r] = acc;
+    if (grp.dense && r == 0) atomicOr((unsigned long long *)&dst.mask[x], 1ull << b);
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
@@ -221,6 +245,8 @@ __global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint
                                             RegDev a, RegDev dst, TabDev et, int e_src_first, uint32_t *ovf,
                                             const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_min[256];   // unranked input slots (data edges)
+  __shared__ int s_nz[BLK / TEAM];
   extern __shared__ uint64_t s_acc[];
   load_rank(s_rank, lut);
   constexpr int teams = BLK / TEAM;
@@ -228,31 +254,36 @@ __global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint
   const int T = grp.T, C = dst.C, Ca = a.C;
   const int TC = T * C;
   const int ra = a.s - 2;
-  uint64_t *acc = s_acc + (int64_t)team * TC;
+  for (int c = threadIdx.x; c < Ca && c < 256; c += BLK) s_min[c] = unrank(lut, ra, c);
+  // accumulators: low and high 32-bit halves of every addend, summed apart
+  // (non-returning LDS adds; the halves cannot overflow), joined at the end
+  uint64_t *acc = s_acc + (int64_t)team * 2 * TC;
   const int64_t N = nentries(grp, Lout);
   uint64_t ofm = 0;
   for (int64_t e0 = (int64_t)blockIdx.x * teams; e0 < N; e0 += (int64_t)gridDim.x * teams) {
     const int64_t e = e0 + team;
     const bool valid = e < N;
     __syncthreads();
-    for (int q = lane; q < TC; q += TEAM) acc[q] = 0;
+    for (int q = lane; q < 2 * TC; q += TEAM) acc[q] = 0;
+    if (lane == 0) s_nz[team] = 0;
     __syncthreads();
     int64_t w = 0;
     int b = 0;
     if (valid) entry_vb(grp, Lout, e, w, b);
     const int64_t u = valid ? grp.src[b] : 0;
     if (valid && w < u) {
-      for (int64_t ee = g.rp[w] + lane; ee < g.rp[w + 1]; ee += TEAM) {
-        const int64_t v = g.col[ee];
-        if (v >= u) break;
-        const int64_t id = entry_of(grp, Lin, v, b);
-        if (id < 0) continue;
-        const uint64_t *ar = a.val + id * (int64_t)T * Ca;
-        for (int t = 0; t < T; t++) {
-          const int cu = colr[(int64_t)t * g.n + u], cw = colr[(int64_t)t * g.n + w],
-                    cv = colr[(int64_t)t * g.n + v];
-          if (cu == cw || cv == cu || cv == cw) continue;
-          const uint64_t *at = ar + t * Ca;
+      for (int t = 0; t < T; t++) {
+        const int cu = colr[(int64_t)t * g.n + u], cw = colr[(int64_t)t * g.n + w];
+        if (cu == cw) continue;
+        uint64_t *at_acc = acc + 2 * t * C;
+        for (int64_t ee = g.rp[w] + lane; ee < g.rp[w + 1]; ee += TEAM) {
+          const int64_t v = g.col[ee];
+          if (v >= u) break;
+          const int64_t id = row_of(grp, Lin, a, v, b);
+          if (id < 0) continue;
+          const int cv = colr[(int64_t)t * g.n + v];
+          if (cv == cu || cv == cw) continue;
+          const uint64_t *at = a.val + (id * T + t) * Ca;
           if (!et.val) {
             for (int c0 = 0; c0 < Ca; c0 += 4) {
               uint64_t x[4];
@@ -261,11 +292,11 @@ __global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint
 #pragma unroll
               for (int q = 0; q < 4; q++) {
                 if (!x[q]) continue;
-                const uint32_t R = spread2(unrank(lut, ra, c0 + q), cu, cv);
+                const uint32_t R = spread2(s_min[c0 + q], cu, cv);
                 if ((R >> cw) & 1u) continue;
                 const int o = s_rank[squeeze2(R | (1u << cv), cu, cw)];
-                unsigned long long old = atomicAdd((unsigned long long *)&acc[t * C + o], (unsigned long long)x[q]);
-                if ((uint64_t)old + x[q] < (uint64_t)old) ofm |= 1ull << t;
+                atomicAdd((unsigned long long *)&at_acc[2 * o], (unsigned long long)(x[q] & 0xffffffffull));
+                atomicAdd((unsigned long long *)&at_acc[2 * o + 1], (unsigned long long)(x[q] >> 32));
               }
             }
           } else {
@@ -290,8 +321,8 @@ __global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint
                 s1 = (s1 - 1) & R;
               }
               if (sum) {
-                unsigned long long old = atomicAdd((unsigned long long *)&acc[t * C + co], (unsigned long long)sum);
-                if ((uint64_t)old + sum < (uint64_t)old) of = true;
+                atomicAdd((unsigned long long *)&at_acc[2 * co], (unsigned long long)(sum & 0xffffffffull));
+                atomicAdd((unsigned long long *)&at_acc[2 * co + 1], (unsigned long long)(sum >> 32));
               }
               if (of) ofm |= 1ull << t;
             }
@@ -302,7 +333,24 @@ __global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint
     __syncthreads();
     if (valid) {
       uint64_t *drow = dst.val + e * (int64_t)TC;
-      for (int q = lane; q < TC; q += TEAM) drow[q] = acc[q];
+      bool nz = false;
+      for (int q = lane; q < TC; q += TEAM) {
+        const uint64_t lo = acc[2 * q], hi = acc[2 * q + 1];
+        // value = hi * 2^32 + lo; both halves are sums of 32-bit parts
+        const uint64_t hs = hi + (lo >> 32);
+        if (hs >> 32) ofm |= 1ull << (q / C);
+        const uint64_t v = (hs << 32) | (lo & 0xffffffffull);
+        drow[q] = v;
+        nz |= v != 0;
+      }
+      if (nz) s_nz[team] = 1;
+    }
+    if (grp.dense) {
+      __syncthreads();
+      if (valid && lane == 0) {
+        if (s_nz[team]) atomicOr((unsigned long long *)&dst.mask[w], 1ull << b);
+        else atomicAnd((unsigned long long *)&dst.mask[w], ~(1ull << b));
+      }
     }
   }
   flag_trials(ovf, ofm);
@@ -325,6 +373,7 @@ __global__ __launch_bounds__(BLK) void k_nj(GroupDev grp, int64_t n, const uint8
     int64_t v;
     int b;
     entry_vb(grp, L, e, v, b);
+    if (!live(grp, a, v, b)) continue;
     const int64_t u = grp.src[b];
     uint64_t acc = 0;
     bool of = false;
@@ -363,12 +412,28 @@ __global__ __launch_bounds__(BLK) void k_axpy(GroupDev grp, LevelDev L, RegDev a
   uint64_t ofm = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     bool of = false;
+    bool on = true;
+    if (grp.dense) {
+      const int64_t row = i / ((int64_t)T * C);
+      on = (a.mask[row / grp.B] >> (row % grp.B)) & 1ull;
+      if (!on && !first) continue;
+    }
     uint64_t y = first ? 0 : dst.val[i];
-    add_ck(y, mul_ck(w, a.val[i], of), of);
+    if (on) add_ck(y, mul_ck(w, a.val[i], of), of);
     dst.val[i] = y;
     if (of) ofm |= 1ull << ((i / C) % T);
   }
   flag_trials(ovf, ofm);
+}
+
+// dst.mask = (first ? 0 : dst.mask) | a.mask
+__global__ void k_mask_or(const uint64_t *am, uint64_t *dm, int64_t n, int first) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dm[i] = first ? am[i] : (dm[i] | am[i]);
+}
+__global__ void k_fill_v(uint64_t *p, int64_t n, uint64_t x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = x;
 }
 
 // ------------------------------------------------------------------ root merge
@@ -387,14 +452,16 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
   const int64_t N = nentries(grp, La) * per;
   uint64_t lo0 = 0, hi0 = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
+    const int64_t e = i / per;
+    if (grp.dense && !((a.mask[e / grp.B] >> (e % grp.B)) & 1ull)) continue;
     const uint64_t x = a.val[i];
     if (!x) continue;
-    const int64_t e = i / per;
     const int r = (int)(i - e * per), t = r / Ca, c = r - t * Ca;
     int64_t v;
     int b;
     entry_vb(grp, La, e, v, b);
-    const int64_t eb = entry_of(grp, Lb, v, b);
+    if (!live(grp, a, v, b)) continue;
+    const int64_t eb = row_of(grp, Lb, bb, v, b);
     if (eb < 0) continue;
     const int64_t u = grp.src[b];
     const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
@@ -447,8 +514,8 @@ __global__ __launch_bounds__(BLK) void k_munary(GroupDev grp, int64_t n, const u
     int b;
     entry_vb(grp, La, e, v, b);
     const int64_t u = grp.src[b];
-    if (v >= u) continue;
-    const int64_t eb = entry_of(grp, Lb, v, b);
+    if (v >= u || !live(grp, a, v, b)) continue;
+    const int64_t eb = row_of(grp, Lb, bb, v, b);
     if (eb < 0) continue;
     const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
     if (cu == cv) continue;
@@ -498,7 +565,7 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
     int b;
     entry_vb(grp, La, e, x, b);
     const int64_t u = grp.src[b];
-    if (x >= u) continue;
+    if (x >= u || !live(grp, a, x, b)) continue;
     const int cu = colr[(int64_t)t * g.n + u], cx = colr[(int64_t)t * g.n + x];
     if (cu == cx) continue;
     const uint64_t *ar = a.val + (e * T + t) * Ca;
@@ -506,7 +573,7 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
     for (int64_t ee = g.rp[x]; ee < g.rp[x + 1]; ee++) {
       const int64_t y = g.col[ee];
       if (y >= u) break;
-      const int64_t eb = entry_of(grp, Lb, y, b);
+      const int64_t eb = row_of(grp, Lb, bb, y, b);
       if (eb < 0) continue;
       const int cy = colr[(int64_t)t * g.n + y];
       if (cy == cx || cy == cu) continue;
@@ -570,7 +637,7 @@ __global__ __launch_bounds__(BLK) void k_medge_t(GraphDev g, GroupDev grp, const
     if (j >= lowcnt[u]) continue;
     const int64_t es = g.rp[u] + j;
     const int64_t y = g.col[es];
-    const int64_t eb = entry_of(grp, Lb, y, b);
+    const int64_t eb = row_of(grp, Lb, bb, y, b);
     if (eb < 0) continue;
     const int cu = colr[(int64_t)t * g.n + u], cy = colr[(int64_t)t * g.n + y];
     if (cu == cy) continue;
@@ -635,12 +702,13 @@ void launch_level_init(const GraphDev &g, const GroupDev &grp, const int32_t *lo
 
 static void compact(const GroupDev &grp, LevelDev L, hipStream_t st) {
   const int64_t nf = grp.n_lim * (int64_t)grp.B;
-  const int nb = (int)((nf + CH - 1) / CH);
+  const int64_t nv = grp.n_lim;
+  const int nb = (int)((nv + CH - 1) / CH);
   // the chunk counts live past the end of the list (which holds at most nf entries)
   uint32_t *bcnt = (uint32_t *)(L.list + nf);
-  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.flag, nf, bcnt);
+  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.flag, L.vflag, nv, grp.B, bcnt);
   hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(BLK), 0, st, bcnt, nb, L.cnt);
-  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.flag, nf, bcnt, grp.B, L.idx, L.list);
+  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.flag, L.vflag, nv, bcnt, grp.B, L.idx, L.list);
 }
 
 void launch_level_next(const GraphDev &g, const GroupDev &grp, LevelDev Lin, LevelDev Lout, hipStream_t st) {
@@ -667,14 +735,15 @@ void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
                RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st) {
   const int TC = grp.T * dst.C;
   const int gr = grp.dense ? (int)std::max<int64_t>(1, std::min<int64_t>(grp.n_lim * grp.B / 4, 65536)) : 8192;
-  if ((size_t)16 * TC * 8 <= 48 * 1024)
-    hipLaunchKernelGGL(k_ej<16>, dim3(gr), dim3(BLK), (size_t)16 * TC * 8, st, g, grp, colr, Lin, Lout, a, dst, etab,
+  const size_t row = (size_t)2 * TC * 8;  // two accumulator words per slot
+  if (16 * row <= 48 * 1024)
+    hipLaunchKernelGGL(k_ej<16>, dim3(gr), dim3(BLK), 16 * row, st, g, grp, colr, Lin, Lout, a, dst, etab,
                        e_src_first, ovf, cur_lut());
-  else if ((size_t)4 * TC * 8 <= 48 * 1024)
-    hipLaunchKernelGGL(k_ej<64>, dim3(gr), dim3(BLK), (size_t)4 * TC * 8, st, g, grp, colr, Lin, Lout, a, dst, etab,
+  else if (4 * row <= 48 * 1024)
+    hipLaunchKernelGGL(k_ej<64>, dim3(gr), dim3(BLK), 4 * row, st, g, grp, colr, Lin, Lout, a, dst, etab,
                        e_src_first, ovf, cur_lut());
   else
-    hipLaunchKernelGGL(k_ej<256>, dim3(gr), dim3(BLK), (size_t)TC * 8, st, g, grp, colr, Lin, Lout, a, dst, etab,
+    hipLaunchKernelGGL(k_ej<256>, dim3(gr), dim3(BLK), row, st, g, grp, colr, Lin, Lout, a, dst, etab,
                        e_src_first, ovf, cur_lut());
 }
 
@@ -688,6 +757,14 @@ void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t
                  hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, L, a, dst, w, first,
                      ovf);
+  if (grp.dense)
+    hipLaunchKernelGGL(k_mask_or, dim3((unsigned)std::min<int64_t>((grp.n_lim + BLK - 1) / BLK, 8192)), dim3(BLK), 0,
+                       st, a.mask, dst.mask, grp.n_lim, first);
+}
+void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_v, dim3((unsigned)std::min<int64_t>((n + BLK - 1) / BLK, 8192)), dim3(BLK), 0, st, p, n,
+                     x);
 }
 
 void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,

@@ -30,13 +30,15 @@ struct LevelDev {
   int64_t *list;   // [entries]
   uint32_t *cnt;   // number of entries
   uint8_t *flag;   // [n_lim * B] marks while the level is built
+  uint8_t *vflag;  // [n_lim] per-vertex marks while the level is built
 };
 
 // A frontier register: one row of T * C slots per entry of its level.
 struct RegDev {
   uint64_t *val;
-  int C;  // slots per (entry, trial)
-  int s;  // signature size
+  uint64_t *mask;  // dense groups: per vertex, bit b set when row (v, b) may be nonzero
+  int C;           // slots per (entry, trial)
+  int s;           // signature size
 };
 
 // The group being processed.
@@ -96,6 +98,7 @@ void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
                TabDev ntab, uint32_t *ovf, hipStream_t st);
 void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,
                  hipStream_t st);
+void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st);
 void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,
                   uint64_t w, AccDev acc, hipStream_t st);
 void launch_munary(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,
