@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one 1 GiB device-to-device copy, so that hardware byte counters "
+                         "collected over this run can be scaled against a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -56,24 +59,55 @@ def query_of(name):
     raise KeyError(name)
 
 
-def roofline(cc, dg, q, seed, trials):
-    """One untimed solve with per-kernel HIP-event timing; the dominant kernel
-    (largest summed time) against the HBM peak, from its algorithmic bytes."""
-    cc.profile_take()
-    cc.profile_enable(True)
-    try:
-        cc.count(dg, q, seed, trials)
-    finally:
-        cc.profile_enable(False)
-    st = cc.profile_take()
-    name = max(st, key=lambda x: st[x][1])
-    launches, secs, byts = st[name]
+KERNEL_OF = {  # profiled op name -> the HIP kernel that runs it
+    "edgejoin": "k_ej", "nodejoin": "k_nj", "axpy": "k_axpy", "merge_root": "k_mroot", "init": "k_init",
+    "merge_u": "k_munary", "merge_v": "k_munary", "merge_edge": "k_medge", "merge_edge_t": "k_medge_t",
+    "level_build_sparse": "level build", "light": "k_light", "leaf": "k_leaf", "root_single": "k_root_single",
+}
+
+
+def kernel_of(op_name):
+    base = op_name.rsplit("_", 1)[0] if op_name.endswith(("_dense", "_sparse")) else op_name
+    return KERNEL_OF.get(base, base)
+
+
+def traffic_record(kernel, launches):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_cl1m_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1602_04478_amd", "csrc", rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def roofline(stats):
+    """The dominant kernel (largest summed time over the timed steps, timed
+    with HIP events on the library's stream) against the HBM peak, from the
+    algorithmic bytes its launches counted."""
+    per_kernel = {}
+    for op, (launches, secs, byts, _work) in stats.items():
+        kn = kernel_of(op)
+        a = per_kernel.setdefault(kn, [0, 0.0, 0.0, []])
+        a[0] += launches
+        a[1] += secs
+        a[2] += byts
+        a[3].append(op)
+    name = max(per_kernel, key=lambda x: per_kernel[x][1])
+    launches, secs, byts, ops = per_kernel[name]
     ach = byts / secs / 1e9 if secs > 0 else 0.0
-    roof = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "launches": launches,
-            "avg_launch_ms": 1000.0 * secs / max(1, launches),
-            "alg_bytes_per_launch": byts / max(1, launches)}
-    kern = {k: {"launches": v[0], "ms": 1000.0 * v[1], "alg_GB": v[2] / 1e9} for k, v in st.items()}
+    traffic = traffic_record(name, launches)
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": name, "ops": sorted(ops), "launches": launches,
+            "avg_launch_ms": 1000.0 * secs / max(1, launches), "alg_bytes_per_launch": byts / max(1, launches)}
+    kern = {k: {"launches": v[0], "ms": 1000.0 * v[1], "alg_GB": v[2] / 1e9} for k, v in stats.items()}
+    for k, v in stats.items():
+        if any(v[3]):
+            kern[k]["pairs_scanned"], kern[k]["rows_read"], kern[k]["rows_written"] = v[3]
     return roof, kern
 
 
@@ -114,16 +148,31 @@ def main():
     k, E = query_of(qname)
     dg = cc.Graph.from_csr(g)
     q = cc.Query(k, E)
+    if a.copy_probe:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     for i in range(a.warmup):
         cc.count(dg, q, seed0 + 1000 + i, trials)
     times, results = [], []
+    prof = not a.no_profile
+    if prof:
+        cc.profile_take()
+        cc.profile_enable(True)
     t_all = time.perf_counter()
     for i in range(a.steps):
         t1 = time.perf_counter()
         counts, ovf, exact, est = cc.count(dg, q, seed0 + i, trials)
         times.append(time.perf_counter() - t1)
         results.append((int(counts[0]), int(ovf[0])))
+        print(f"[bench] step {i}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
     total = time.perf_counter() - t_all
+    if prof:
+        cc.profile_enable(False)
+        stats = cc.profile_take()
     ms = 1000.0 * total / a.steps
     value = trials * g.m / (total / a.steps)
     out = {
@@ -144,8 +193,8 @@ def main():
                    "k": k, "trials": trials},
         "counts": results,
     }
-    if not a.no_profile:
-        out["roofline"], out["kernels"] = roofline(cc, dg, q, seed0, trials)
+    if prof:
+        out["roofline"], out["kernels"] = roofline(stats)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, k, E, seed0, a.cpu_sample_seconds)
     out["graph_gen_s"] = t_gen

@@ -221,6 +221,8 @@ typedef struct {
   uint64_t launches;
   double seconds;  /* summed event-measured duration */
   double bytes;    /* algorithmic bytes (EdgeJoin only; 0 elsewhere) */
+  uint64_t work[3]; /* EdgeJoin: (entry, trial, lower neighbour) pairs scanned, input rows read,
+                       output rows written; 0 elsewhere */
 } cc_kernel_stat;
 
 cc_status cc_profile_enable(int32_t on);

@@ -38,7 +38,7 @@ class U128(ctypes.Structure):
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("work", ctypes.c_uint64 * 3)]
 
 
 class Tuning(ctypes.Structure):
@@ -289,11 +289,13 @@ def profile_enable(on: bool = True):
 
 
 def profile_take():
-    """Read and reset per-kernel statistics: {name: (launches, seconds, algorithmic bytes)}."""
+    """Read and reset per-kernel statistics:
+    {name: (launches, seconds, algorithmic bytes, (scanned pairs, rows read, rows written))}."""
     cap = 256
     buf = (KernelStat * cap)()
     n = ctypes.c_int32()
     _check(lib().cc_profile_read(buf, cap, ctypes.byref(n)))
-    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].seconds), float(buf[i].bytes))
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].seconds), float(buf[i].bytes),
+                                   tuple(int(x) for x in buf[i].work))
             for i in range(min(n.value, cap))}
 

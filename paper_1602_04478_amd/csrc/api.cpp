@@ -238,10 +238,11 @@ cc_status cc_profile_read(cc_kernel_stat *out, int32_t cap, int32_t *len) {
     *len = (int32_t)v.size();
     for (int32_t i = 0; out && i < cap && i < (int32_t)v.size(); i++) {
       std::memset(out[i].name, 0, sizeof(out[i].name));
-      std::strncpy(out[i].name, v[i].first.c_str(), sizeof(out[i].name) - 1);
-      out[i].launches = (uint64_t)v[i].second[0];
-      out[i].seconds = v[i].second[1];
-      out[i].bytes = v[i].second[2];
+      std::strncpy(out[i].name, v[i].name.c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = v[i].launches;
+      out[i].seconds = v[i].seconds;
+      out[i].bytes = v[i].bytes;
+      for (int j = 0; j < 3; j++) out[i].work[j] = v[i].work[j];
     }
   });
 }

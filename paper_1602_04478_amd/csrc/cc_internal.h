@@ -152,7 +152,13 @@ uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptio
 void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t stream);
 
 void profile_enable(bool on);
-std::vector<std::pair<std::string, std::array<double, 3>>> profile_read();
+struct KernelProfile {
+  std::string name;
+  uint64_t launches;
+  double seconds, bytes;
+  uint64_t work[3];
+};
+std::vector<KernelProfile> profile_read();
 
 double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf);
 

@@ -62,7 +62,7 @@ struct RegBuf {
   DevMem val, mask;
 };
 struct LevelBuf {
-  DevMem idx, list, cnt, flag, vflag;
+  DevMem m, base, list, cnt, bcnt;
 };
 
 int table_C(const Plan &p, int blk) {
@@ -148,12 +148,34 @@ Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &o
 struct ProfStat {
   uint64_t launches = 0;
   double seconds = 0, bytes = 0;
+  uint64_t work[3] = {0, 0, 0};
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::map<std::string, ProfStat> g_prof;
 
 // Records of the launches of one call (events are resolved at its end).
+// events for per-launch timing, reused across solves
+std::mutex g_ev_mu;
+std::vector<hipEvent_t> g_ev_pool;
+hipEvent_t take_event() {
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    if (!g_ev_pool.empty()) {
+      hipEvent_t e = g_ev_pool.back();
+      g_ev_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+void give_event(hipEvent_t e) {
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  g_ev_pool.push_back(e);
+}
+
 struct Profiler {
   bool on = false;
   hipStream_t st;
@@ -177,9 +199,6 @@ struct Profiler {
     if (!on) return nullptr;
     Rec r;
     r.name = name;
-    HIP_CHECK(hipEventCreate(&r.a));
-    HIP_CHECK(hipEventCreate(&r.b));
-    HIP_CHECK(hipEventRecord(r.a, st));
     r.ctr = -1;
     uint64_t *c = nullptr;
     if (counters && nctr < 65536) {
@@ -187,6 +206,9 @@ struct Profiler {
       c = ctrmem.as<uint64_t>() + 3 * r.ctr;
       launch_fill_u64(c, 3, st);
     }
+    r.a = take_event();
+    r.b = take_event();
+    HIP_CHECK(hipEventRecord(r.a, st));
     r.per_scan = per_scan;
     r.per_active = per_active;
     r.per_entry = per_entry;
@@ -209,10 +231,12 @@ struct Profiler {
       ProfStat &p = g_prof[r.name];
       p.launches++;
       p.seconds += ms * 1e-3;
-      if (r.ctr >= 0)
+      if (r.ctr >= 0) {
         p.bytes += h[3 * r.ctr] * r.per_scan + h[3 * r.ctr + 1] * r.per_active + h[3 * r.ctr + 2] * r.per_entry;
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
+        for (int i = 0; i < 3; i++) p.work[i] += h[3 * r.ctr + i];
+      }
+      give_event(r.a);
+      give_event(r.b);
     }
     recs.clear();
   }
@@ -225,10 +249,13 @@ void profile_enable(bool on) {
   g_prof_on = on;
 }
 
-std::vector<std::pair<std::string, std::array<double, 3>>> profile_read() {
+std::vector<KernelProfile> profile_read() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  std::vector<std::pair<std::string, std::array<double, 3>>> v;
-  for (auto &kv : g_prof) v.push_back({kv.first, {(double)kv.second.launches, kv.second.seconds, kv.second.bytes}});
+  std::vector<KernelProfile> v;
+  for (auto &kv : g_prof) {
+    const ProfStat &p = kv.second;
+    v.push_back({kv.first, p.launches, p.seconds, p.bytes, {p.work[0], p.work[1], p.work[2]}});
+  }
   g_prof.clear();
   return v;
 }
@@ -373,24 +400,21 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
   const size_t nf_max = (size_t)nlim_max * Bmax;
   auto ensure_level = [&](int d) {
     LevelBuf &L = levels[d];
-    if (L.flag.bytes >= nf_max) return;
-    L.flag.alloc(nf_max);
-    launch_fill_u8(L.flag.as<uint8_t>(), (int64_t)nf_max, st);
-    L.vflag.alloc(nlim_max);
-    launch_fill_u8(L.vflag.as<uint8_t>(), (int64_t)nlim_max, st);
-    L.idx.alloc(sizeof(int32_t) * nf_max);
-    launch_fill_u8(L.idx.as<uint8_t>(), (int64_t)(sizeof(int32_t) * nf_max), st, 0xff);
-    L.list.alloc(sizeof(int64_t) * (nf_max + nf_max / 4096 + 64));
+    if (L.m.bytes >= sizeof(uint64_t) * (size_t)nlim_max) return;
+    L.m.alloc(sizeof(uint64_t) * (size_t)nlim_max);
+    launch_fill_u64(L.m.as<uint64_t>(), nlim_max, st);
+    L.base.alloc(sizeof(uint32_t) * (size_t)nlim_max);
+    L.list.alloc(sizeof(int64_t) * nf_max);
     L.cnt.alloc(sizeof(uint32_t));
-    HIP_CHECK(hipMemsetAsync(L.cnt.p, 0, sizeof(uint32_t), st));
+    L.bcnt.alloc(sizeof(uint32_t) * (size_t)level_chunks(nlim_max));
   };
   auto leveldev = [&](int d) {
     LevelDev L;
-    L.idx = levels[d].idx.as<int32_t>();
+    L.m = levels[d].m.as<uint64_t>();
+    L.base = levels[d].base.as<uint32_t>();
     L.list = levels[d].list.as<int64_t>();
     L.cnt = levels[d].cnt.as<uint32_t>();
-    L.flag = levels[d].flag.as<uint8_t>();
-    L.vflag = levels[d].vflag.as<uint8_t>();
+    L.bcnt = levels[d].bcnt.as<uint32_t>();
     return L;
   };
 
@@ -497,7 +521,17 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
           std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
           if (op.kind == OP_INIT) build(1);
           if (op.kind == OP_EJ) build(P.reg_depth[op.dst]);
-          prof.begin(nm.c_str(), false, 0, 0, 0);
+          if (op.kind == OP_EJ) {
+            // algorithmic bytes: a 4-byte neighbour id per scanned pair, an
+            // input row (plus the annotated edge's table row) per relaxation,
+            // an output row per entry
+            const double Cin = (double)slots_pair(k, P.reg_s[op.a]), Cout = (double)slots_pair(k, P.reg_s[op.dst]);
+            const double Ce = op.tab >= 0 ? (double)table_C(p, op.tab) : 0.0;
+            grp.prof = prof.begin(nm.c_str(), true, 4.0, 8.0 * (Cin + Ce), 8.0 * Tg * Cout);
+          } else {
+            grp.prof = nullptr;
+            prof.begin(nm.c_str(), false, 0, 0, 0);
+          }
           switch (op.kind) {
             case OP_INIT: {
               RegDev d = regdev(op.dst);

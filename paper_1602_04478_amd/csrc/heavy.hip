@@ -5,10 +5,11 @@
 // reaches (every register of that depth has a row per entry, whatever its
 // annotations, since reachability does not depend on colours or tables).
 // Dense groups -- the sources with the widest reach -- keep a row for every
-// (v, b) with v < n_lim, rows of unreachable pairs holding zeros.  Sparse groups
-// list their entries: a level is built by marking (plain byte stores, no
-// atomics) and a deterministic compaction pass that numbers the marks in
-// vertex order.
+// (v, b) with v < n_lim, and a per-vertex mask per register of the rows that
+// may be nonzero.  Sparse groups list their entries: a level is a per-vertex
+// 64-bit mark word (bit b: source b reaches v) built with atomic ORs, then a
+// deterministic compaction numbers the marks in (vertex, source) order, so the
+// entry of (v, b) is base[v] + popcount of the marks of v below b.
 //
 // EdgeJoin is a pull: a team of lanes owns one output entry (w, b) and strides
 // over w's neighbours below u_b; each lane reads the whole row of its
@@ -30,7 +31,8 @@ namespace {
 
 using namespace dev;
 
-constexpr int CH = 8192;  // flags per compaction chunk (32 per thread)
+constexpr int CPER = 16;           // vertices per thread in a compaction chunk
+constexpr int CH = BLK * CPER;     // vertices per compaction chunk
 
 __device__ __forceinline__ int64_t nentries(const GroupDev &g, const LevelDev &L) {
   return g.dense ? g.n_lim * (int64_t)g.B : (int64_t)(*L.cnt);
@@ -45,18 +47,28 @@ __device__ __forceinline__ void entry_vb(const GroupDev &g, const LevelDev &L, i
     b = (int)(x & 63);
   }
 }
+__device__ __forceinline__ int64_t sparse_entry(const LevelDev &L, int64_t v, int b) {
+  const uint64_t mm = L.m[v];
+  const int64_t bs = L.base[v];  // loaded together with the marks
+  return ((mm >> b) & 1ull) ? bs + __popcll(mm & ((1ull << b) - 1ull)) : (int64_t)-1;
+}
 __device__ __forceinline__ int64_t entry_of(const GroupDev &g, const LevelDev &L, int64_t v, int b) {
   if (g.dense) return v < g.n_lim ? v * g.B + b : -1;
-  return L.idx[v * g.B + b];
+  return sparse_entry(L, v, b);
 }
 // row of register r for (v, b), or -1 when it has none (sparse) or is known
 // to be zero (dense: its activity bit is clear)
 __device__ __forceinline__ int64_t row_of(const GroupDev &g, const LevelDev &L, const RegDev &r, int64_t v, int b) {
   if (g.dense) return (v < g.n_lim && ((r.mask[v] >> b) & 1ull)) ? v * g.B + b : -1;
-  return L.idx[v * g.B + b];
+  return sparse_entry(L, v, b);
 }
 __device__ __forceinline__ bool live(const GroupDev &g, const RegDev &r, int64_t v, int b) {
   return !g.dense || ((r.mask[v] >> b) & 1ull);
+}
+
+__device__ __forceinline__ void mark(uint64_t *m, int64_t v, int b) {
+  const uint64_t bit = 1ull << b;
+  if (!(m[v] & bit)) atomicOr((unsigned long long *)&m[v], (unsigned long long)bit);
 }
 
 // ------------------------------------------------------------------ levels (sparse groups)
@@ -67,9 +79,7 @@ __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int
     const int b = (int)(i / max_low), j = (int)(i - (int64_t)b * max_low);
     const int64_t u = grp.src[b];
     if (j >= lowcnt[u]) continue;
-    const int64_t x = g.col[g.rp[u] + j];
-    L.flag[x * grp.B + b] = 1;
-    L.vflag[x] = 1;
+    mark(L.m, g.col[g.rp[u] + j], b);
   }
 }
 
@@ -86,27 +96,36 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
     for (int64_t ee = g.rp[v] + lane; ee < g.rp[v + 1]; ee += TEAM) {
       const int64_t w = g.col[ee];
       if (w >= u) break;
-      Lout.flag[w * grp.B + b] = 1;
-      Lout.vflag[w] = 1;
+      mark(Lout.m, w, b);
     }
   }
 }
 
-// Compaction walks vertices in chunks of CH (32 per thread): only vertices
-// with their per-vertex mark set have their B source marks read.
-__device__ __forceinline__ uint32_t count_marks(const uint8_t *flag, int64_t v, int B) {
-  uint32_t c = 0;
-  for (int b = 0; b < B; b++) c += flag[v * B + b] != 0;
-  return c;
+// exclusive prefix sum over the workgroup; returns the total in *tot
+__device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t *s, uint32_t &tot) {
+  s[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 1; o < BLK; o <<= 1) {
+    const uint32_t y = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += y;
+    __syncthreads();
+  }
+  tot = s[BLK - 1];
+  const uint32_t r = s[threadIdx.x] - x;
+  __syncthreads();
+  return r;
 }
 
-// count marks per chunk
-__global__ void k_cmp_count(const uint8_t *flag, const uint8_t *vflag, int64_t nv, int B, uint32_t *bcnt) {
+// marks per chunk (thread t reads vertices lo + i * BLK + t: coalesced)
+__global__ void k_cmp_count(const uint64_t *m, int64_t nv, uint32_t *bcnt) {
   __shared__ uint32_t s[BLK];
-  const int64_t lo = (int64_t)blockIdx.x * CH + (int64_t)threadIdx.x * (CH / BLK);
+  const int64_t lo = (int64_t)blockIdx.x * CH;
   uint32_t c = 0;
-  for (int i = 0; i < CH / BLK; i++)
-    if (lo + i < nv && vflag[lo + i]) c += count_marks(flag, lo + i, B);
+  for (int i = 0; i < CPER; i++) {
+    const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
+    if (v < nv) c += __popcll(m[v]);
+  }
   s[threadIdx.x] = c;
   __syncthreads();
   for (int o = BLK / 2; o > 0; o >>= 1) {
@@ -118,76 +137,39 @@ __global__ void k_cmp_count(const uint8_t *flag, const uint8_t *vflag, int64_t n
 
 // exclusive scan of the chunk counts (one workgroup); total into *cnt
 __global__ void k_cmp_scan(uint32_t *bcnt, int nb, uint32_t *cnt) {
-  __shared__ uint32_t s[BLK + 1];
+  __shared__ uint32_t s[BLK];
   const int per = (nb + BLK - 1) / BLK;
   const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
   uint32_t sum = 0;
   for (int i = lo; i < hi; i++) sum += bcnt[i];
-  s[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < BLK; i++) {
-      uint32_t x = s[i];
-      s[i] = run;
-      run += x;
-    }
-    s[BLK] = run;
-    *cnt = run;
-  }
-  __syncthreads();
-  uint32_t run = s[threadIdx.x];
+  uint32_t tot;
+  uint32_t run = block_scan(sum, s, tot);
   for (int i = lo; i < hi; i++) {
-    uint32_t x = bcnt[i];
+    const uint32_t x = bcnt[i];
     bcnt[i] = run;
     run += x;
   }
+  if (threadIdx.x == 0) *cnt = tot;
 }
 
-// number the marks in (vertex, source) order: idx and list, clearing the marks
-__global__ void k_cmp_emit(uint8_t *flag, uint8_t *vflag, int64_t nv, const uint32_t *boff, int B, int32_t *idx,
-                           int64_t *list) {
+// number the marks: base[v] and the entry list, in (v, b) order
+__global__ void k_cmp_emit(const uint64_t *m, int64_t nv, const uint32_t *boff, uint32_t *base, int64_t *list) {
   __shared__ uint32_t s[BLK];
-  const int per = CH / BLK;
-  const int64_t lo = (int64_t)blockIdx.x * CH + (int64_t)threadIdx.x * per;
-  uint32_t c = 0;
-  for (int i = 0; i < per; i++)
-    if (lo + i < nv && vflag[lo + i]) c += count_marks(flag, lo + i, B);
-  s[threadIdx.x] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < BLK; i++) {
-      uint32_t x = s[i];
-      s[i] = run;
-      run += x;
+  const int64_t lo = (int64_t)blockIdx.x * CH;
+  uint32_t run = boff[blockIdx.x];
+  for (int i = 0; i < CPER; i++) {
+    const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
+    const uint64_t mm = v < nv ? m[v] : 0;
+    uint32_t tot;
+    const uint32_t id0 = run + block_scan((uint32_t)__popcll(mm), s, tot);
+    if (v < nv) {
+      base[v] = id0;
+      uint32_t id = id0;
+      for (uint64_t r = mm; r; r &= r - 1) list[id++] = v * 64 + __builtin_ctzll(r);
     }
-  }
-  __syncthreads();
-  uint32_t id = boff[blockIdx.x] + s[threadIdx.x];
-  for (int i = 0; i < per; i++) {
-    const int64_t v = lo + i;
-    if (v >= nv || !vflag[v]) continue;
-    vflag[v] = 0;
-    for (int b = 0; b < B; b++) {
-      const int64_t f = v * B + b;
-      if (!flag[f]) continue;
-      flag[f] = 0;
-      idx[f] = (int32_t)id;
-      list[id] = v * 64 + b;
-      id++;
-    }
+    run += tot;
   }
 }
-
-__global__ void k_level_reset(GroupDev grp, LevelDev L) {
-  const int64_t N = *L.cnt;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t x = L.list[e];
-    L.idx[(x >> 6) * grp.B + (x & 63)] = -1;
-  }
-}
-__global__ void k_zero_cnt(uint32_t *c) { *c = 0; }
 
 // ------------------------------------------------------------------ INIT
 // dst[(x, b)] for x in the lower prefix of u_b's row:
@@ -240,80 +222,129 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
 // ------------------------------------------------------------------ EdgeJoin
 // dst[(w,b)][R'] = sum over v in N(w), v < u_b, (v,b) an entry of the lower
 // level, of sum over splits R' \ {chi v} = R + Re of a[(v,b)][R] * E(v,w)[Re].
-template <int TEAM>
-__global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout,
-                                            RegDev a, RegDev dst, TabDev et, int e_src_first, uint32_t *ovf,
-                                            const uint16_t *lut) {
+constexpr int WAVE = 64;
+constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
+
+// One wavefront per output entry (w, b); per trial, w's neighbours below u_b
+// are taken 64 at a time in two phases:
+//   gather: lane j looks up neighbour j (its row in the input register and its
+//           colour) and the usable ones are packed into LDS by a ballot;
+//   relax:  the wave walks the packed (neighbour, slot) pairs, lane i taking
+//           pairs i, i + 64, ..., loading four input values before it adds
+//           them, so rows are read contiguously and many loads are in flight.
+// Data edge: input slot c goes to the output slot with chi(v) added (Section
+// 4.3).  Annotated edge: lanes take (neighbour, output slot) pairs and sum the
+// products over the splits of the output signature (EdgeJoin of Section 4.4).
+// Accumulation in LDS in split 32-bit halves (non-returning adds that cannot
+// overflow), joined and checked when the row is written.
+template <bool ANN>
+__global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin,
+                                             LevelDev Lout, RegDev a, RegDev dst, TabDev et, int e_src_first,
+                                             uint32_t *ovf, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
-  __shared__ uint32_t s_min[256];   // unranked input slots (data edges)
-  __shared__ int s_nz[BLK / TEAM];
-  extern __shared__ uint64_t s_acc[];
+  __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
+  __shared__ int64_t s_id[WAVE];  // packed neighbours: input row
+  __shared__ int64_t s_ts[WAVE];  //   annotated edge's table slot
+  __shared__ uint8_t s_cv[WAVE];  //   colour
+  extern __shared__ uint64_t acc[];  // [T][C][2]
   load_rank(s_rank, lut);
-  constexpr int teams = BLK / TEAM;
-  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
   const int T = grp.T, C = dst.C, Ca = a.C;
   const int TC = T * C;
-  const int ra = a.s - 2;
-  for (int c = threadIdx.x; c < Ca && c < 256; c += BLK) s_min[c] = unrank(lut, ra, c);
-  // accumulators: low and high 32-bit halves of every addend, summed apart
-  // (non-returning LDS adds; the halves cannot overflow), joined at the end
-  uint64_t *acc = s_acc + (int64_t)team * 2 * TC;
+  const int ra = a.s - 2, ro = dst.s - 2;
+  const int W = ANN ? C : Ca;  // pairs per neighbour
+  for (int c = threadIdx.x; c < W; c += WAVE) s_um[c] = unrank(lut, ANN ? ro : ra, c);
+  // i / W == (i * magic) >> 32 for i < 64 * 256 (magic = ceil(2^32 / W); 2^32 when W = 1)
+  const uint64_t magic = (0x100000000ull + W - 1) / W;
+  const int lane = threadIdx.x;
+  const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t N = nentries(grp, Lout);
   uint64_t ofm = 0;
-  for (int64_t e0 = (int64_t)blockIdx.x * teams; e0 < N; e0 += (int64_t)gridDim.x * teams) {
-    const int64_t e = e0 + team;
-    const bool valid = e < N;
+  // work counters (profiling): (entry, trial, lower neighbour) pairs scanned,
+  // input rows read, output rows written
+  uint64_t n_scan = 0, n_rows = 0, n_ent = 0;
+  for (int64_t e = blockIdx.x; e < N; e += gridDim.x) {
     __syncthreads();
-    for (int q = lane; q < 2 * TC; q += TEAM) acc[q] = 0;
-    if (lane == 0) s_nz[team] = 0;
-    __syncthreads();
-    int64_t w = 0;
-    int b = 0;
-    if (valid) entry_vb(grp, Lout, e, w, b);
-    const int64_t u = valid ? grp.src[b] : 0;
-    if (valid && w < u) {
+    for (int q = lane; q < 2 * TC; q += WAVE) acc[q] = 0;
+    int64_t w;
+    int b;
+    entry_vb(grp, Lout, e, w, b);
+    const int64_t u = grp.src[b];
+    if (w < u) {
+      const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
       for (int t = 0; t < T; t++) {
         const int cu = colr[(int64_t)t * g.n + u], cw = colr[(int64_t)t * g.n + w];
         if (cu == cw) continue;
         uint64_t *at_acc = acc + 2 * t * C;
-        for (int64_t ee = g.rp[w] + lane; ee < g.rp[w + 1]; ee += TEAM) {
-          const int64_t v = g.col[ee];
-          if (v >= u) break;
-          const int64_t id = row_of(grp, Lin, a, v, b);
-          if (id < 0) continue;
-          const int cv = colr[(int64_t)t * g.n + v];
-          if (cv == cu || cv == cw) continue;
-          const uint64_t *at = a.val + (id * T + t) * Ca;
-          if (!et.val) {
-            for (int c0 = 0; c0 < Ca; c0 += 4) {
+        const uint64_t *abase = a.val + (int64_t)t * Ca;
+        for (int64_t j0 = r0; j0 < r1; j0 += WAVE) {
+          // gather
+          const int64_t ee = j0 + lane;
+          const int64_t v = ee < r1 ? g.col[ee] : INT64_MAX;
+          const bool in = v < u;
+          bool ok = false;
+          int64_t id = -1;
+          int cv = 0;
+          if (in) {
+            id = row_of(grp, Lin, a, v, b);
+            if (id >= 0) {
+              cv = colr[(int64_t)t * g.n + v];
+              ok = cv != cu && cv != cw;
+            }
+          }
+          n_scan += in;
+          n_rows += ok;
+          const uint64_t okm = __ballot(ok);
+          const bool stop = __ballot(!in) != 0;
+          __syncthreads();  // the previous chunk's relax phase is done with the packed lists
+          if (ok) {
+            const int pos = __popcll(okm & lt);
+            s_id[pos] = id;
+            s_cv[pos] = (uint8_t)cv;
+            if (ANN) s_ts[pos] = e_src_first ? g.rev[ee] : ee;
+          }
+          __syncthreads();
+          // relax
+          const int items = __popcll(okm) * W;
+          if (!ANN) {
+            for (int i0 = lane; i0 < items; i0 += 4 * WAVE) {
               uint64_t x[4];
+              int jn[4], c[4];
 #pragma unroll
-              for (int q = 0; q < 4; q++) x[q] = c0 + q < Ca ? at[c0 + q] : 0;
+              for (int q = 0; q < 4; q++) {
+                const int i = i0 + q * WAVE;
+                jn[q] = (int)(((uint64_t)(uint32_t)i * magic) >> 32);
+                c[q] = i - jn[q] * W;
+                x[q] = i < items ? abase[s_id[jn[q]] * T * Ca + c[q]] : 0;
+              }
 #pragma unroll
               for (int q = 0; q < 4; q++) {
                 if (!x[q]) continue;
-                const uint32_t R = spread2(s_min[c0 + q], cu, cv);
+                const int cvq = s_cv[jn[q]];
+                const uint32_t R = spread2(s_um[c[q]], cu, cvq);
                 if ((R >> cw) & 1u) continue;
-                const int o = s_rank[squeeze2(R | (1u << cv), cu, cw)];
+                const int o = s_rank[squeeze2(R | (1u << cvq), cu, cw)];
                 atomicAdd((unsigned long long *)&at_acc[2 * o], (unsigned long long)(x[q] & 0xffffffffull));
                 atomicAdd((unsigned long long *)&at_acc[2 * o + 1], (unsigned long long)(x[q] >> 32));
               }
             }
           } else {
-            const int64_t tslot = e_src_first ? g.rev[ee] : ee;
-            const uint64_t *er = et.val + (tslot * T + t) * et.C;
-            for (int co = 0; co < C; co++) {
-              const uint32_t Rp = spread2(unrank(lut, dst.s - 2, co), cu, cw);
-              if (!((Rp >> cv) & 1u)) continue;
-              const uint32_t R = Rp & ~(1u << cv);
+            for (int i = lane; i < items; i += WAVE) {
+              const int jn = (int)(((uint64_t)(uint32_t)i * magic) >> 32);
+              const int co = i - jn * W;
+              const int cvq = s_cv[jn];
+              const uint32_t Rp = spread2(s_um[co], cu, cw);
+              if (!((Rp >> cvq) & 1u)) continue;
+              const uint32_t R = Rp & ~(1u << cvq);
+              const uint64_t *at = abase + s_id[jn] * T * Ca;
+              const uint64_t *er = et.val + (s_ts[jn] * T + t) * et.C;
               uint64_t sum = 0;
               bool of = false;
               uint32_t s1 = R;
               for (;;) {
                 if (__popc(s1) == ra) {
-                  uint64_t xa = at[s_rank[squeeze2(s1, cu, cv)]];
+                  const uint64_t xa = at[s_rank[squeeze2(s1, cu, cvq)]];
                   if (xa) {
-                    uint64_t y = er[s_rank[squeeze2(R & ~s1, cv, cw)]];
+                    const uint64_t y = er[s_rank[squeeze2(R & ~s1, cvq, cw)]];
                     if (y) add_ck(sum, mul_ck(xa, y, of), of);
                   }
                 }
@@ -327,33 +358,220 @@ __global__ __launch_bounds__(BLK) void k_ej(GraphDev g, GroupDev grp, const uint
               if (of) ofm |= 1ull << t;
             }
           }
+          if (stop) break;
         }
       }
     }
     __syncthreads();
-    if (valid) {
-      uint64_t *drow = dst.val + e * (int64_t)TC;
-      bool nz = false;
-      for (int q = lane; q < TC; q += TEAM) {
-        const uint64_t lo = acc[2 * q], hi = acc[2 * q + 1];
-        // value = hi * 2^32 + lo; both halves are sums of 32-bit parts
-        const uint64_t hs = hi + (lo >> 32);
-        if (hs >> 32) ofm |= 1ull << (q / C);
-        const uint64_t v = (hs << 32) | (lo & 0xffffffffull);
-        drow[q] = v;
-        nz |= v != 0;
-      }
-      if (nz) s_nz[team] = 1;
+    uint64_t *drow = dst.val + e * (int64_t)TC;
+    bool nz = false;
+    for (int q = lane; q < TC; q += WAVE) {
+      const uint64_t lo = acc[2 * q], hi = acc[2 * q + 1];
+      // value = hi * 2^32 + lo, both halves sums of 32-bit parts
+      const uint64_t hs = hi + (lo >> 32);
+      if (hs >> 32) ofm |= 1ull << (q / C);
+      const uint64_t v = (hs << 32) | (lo & 0xffffffffull);
+      drow[q] = v;
+      nz |= v != 0;
     }
     if (grp.dense) {
-      __syncthreads();
-      if (valid && lane == 0) {
-        if (s_nz[team]) atomicOr((unsigned long long *)&dst.mask[w], 1ull << b);
+      const bool any = __any(nz);
+      if (lane == 0) {
+        if (any) atomicOr((unsigned long long *)&dst.mask[w], 1ull << b);
         else atomicAnd((unsigned long long *)&dst.mask[w], ~(1ull << b));
+        n_ent += any;
       }
+    } else if (lane == 0) {
+      n_ent++;
     }
   }
   flag_trials(ovf, ofm);
+  if (grp.prof) {
+    for (int o = 32; o > 0; o >>= 1) {
+      n_scan += __shfl_xor(n_scan, o);
+      n_rows += __shfl_xor(n_rows, o);
+      n_ent += __shfl_xor(n_ent, o);
+    }
+    if (lane == 0) {
+      atomicAdd((unsigned long long *)&grp.prof[0], (unsigned long long)n_scan);
+      atomicAdd((unsigned long long *)&grp.prof[1], (unsigned long long)n_rows);
+      atomicAdd((unsigned long long *)&grp.prof[2], (unsigned long long)n_ent);
+    }
+  }
+}
+
+// Vertex-major EdgeJoin: one wavefront per output vertex w, lane = (source b,
+// trial t).  All sources of the group share w's neighbour list, so each
+// neighbour v is read once per wave with its per-vertex bits (which sources
+// have an input row at v), and every lane then relaxes its own row (v, b) for
+// its trial into its own LDS column: no atomics, checked 64-bit adds.  The
+// lanes of one pass are the first 64 / T sources among w's output bits.
+template <bool ANN>
+__global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin,
+                                              LevelDev Lout, RegDev a, RegDev dst, TabDev et, int e_src_first,
+                                              uint32_t *ovf, const uint16_t *lut) {
+  __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
+  __shared__ int32_t s_src[WAVE];
+  __shared__ int8_t s_map[WAVE];  // pass slot -> source
+  __shared__ unsigned long long s_live;
+  extern __shared__ uint64_t acc[];  // [C][64]: lane-owned columns
+  load_rank(s_rank, lut);
+  const int T = grp.T, B = grp.B, C = dst.C, Ca = a.C;
+  const int ra = a.s - 2, ro = dst.s - 2;
+  const int W = ANN ? C : Ca;
+  const int lane = threadIdx.x;
+  for (int c = lane; c < W; c += WAVE) s_um[c] = unrank(lut, ANN ? ro : ra, c);
+  s_src[lane] = lane < B ? grp.src[lane] : -1;
+  __syncthreads();
+  const int Bc = WAVE / T;             // sources per pass
+  const int lt = lane % T, lb = lane / T;  // lane's trial, its source's slot in the pass
+  const int64_t n = g.n;
+  uint64_t ofm = 0, n_scan = 0, n_rows = 0, n_ent = 0;
+  for (int64_t w = blockIdx.x; w < grp.n_lim; w += gridDim.x) {
+    // output rows at w: dense -- every source above w (sources descend); sparse -- the marks
+    const uint64_t ob = grp.dense ? (uint64_t)__ballot(lane < B && s_src[lane] > w) : Lout.m[w];
+    if (!ob) {
+      if (grp.dense && lane == 0) dst.mask[w] = 0;
+      continue;
+    }
+    const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
+    const uint64_t obase = grp.dense ? 0 : Lout.base[w];
+    if (lane == 0) s_live = 0;
+    uint64_t rest = ob;
+    while (rest) {
+      // this pass: the first Bc sources of rest
+      const int rk = __popcll(rest & ((1ull << lane) - 1ull));
+      const bool mine = ((rest >> lane) & 1ull) && rk < Bc;
+      __syncthreads();
+      if (mine) s_map[rk] = (int8_t)lane;
+      const uint64_t pass = __ballot(mine);
+      rest &= ~pass;
+      __syncthreads();
+      const int np = __popcll(pass);
+      const int b = lb < np ? s_map[lb] : -1;
+      const int64_t u = b >= 0 ? s_src[b] : 0;
+      int64_t umax = u;  // the neighbours below the pass's largest source
+      for (int o = 32; o > 0; o >>= 1) umax = max(umax, (int64_t)__shfl_xor(umax, o));
+      int cu = 0, cw = 0;
+      bool act = false;
+      if (b >= 0) {
+        cu = colr[(int64_t)lt * n + u];
+        cw = colr[(int64_t)lt * n + w];
+        act = cu != cw;
+      }
+      for (int o = 0; o < C; o++) acc[o * WAVE + lane] = 0;
+      bool of = false;
+      for (int64_t j0 = r0; j0 < r1; j0 += WAVE) {
+        const int64_t ee = j0 + lane;
+        int64_t vj = ee < r1 ? g.col[ee] : INT64_MAX;
+        if (vj >= umax) vj = INT64_MAX;
+        uint64_t inb = 0, mfull = 0;
+        int64_t bj = 0;
+        if (vj != INT64_MAX) {
+          if (grp.dense) {
+            inb = a.mask[vj];
+          } else {
+            mfull = Lin.m[vj];
+            bj = Lin.base[vj];
+            inb = mfull;
+          }
+          inb &= pass;
+        }
+        const uint64_t below = __ballot(vj != INT64_MAX);
+        n_scan += act ? (uint64_t)__popcll(below) : 0;
+        uint64_t todo = __ballot(inb != 0);
+        const bool stop = __ballot(vj == INT64_MAX) != 0;
+        while (todo) {
+          const int jj = __builtin_ctzll(todo);
+          todo &= todo - 1;
+          // every lane takes part in the cross-lane reads (a lane that is
+          // switched off cannot serve as a source)
+          const int64_t v = __shfl(vj, jj);
+          const uint64_t ib = __shfl(inb, jj);
+          const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj);
+          const int64_t vb = grp.dense ? 0 : __shfl(bj, jj);
+          if (!act || v >= u || !((ib >> b) & 1ull)) continue;
+          const int cv = colr[(int64_t)lt * n + v];
+          if (cv == cu || cv == cw) continue;
+          const int64_t id = grp.dense ? v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
+          n_rows++;
+          const uint64_t *row = a.val + (id * T + lt) * Ca;
+          if (!ANN) {
+            for (int c = 0; c < Ca; c++) {
+              const uint64_t x = row[c];
+              if (!x) continue;
+              const uint32_t R = spread2(s_um[c], cu, cv);
+              if ((R >> cw) & 1u) continue;
+              const int o = s_rank[squeeze2(R | (1u << cv), cu, cw)];
+              add_ck(acc[o * WAVE + lane], x, of);
+            }
+          } else {
+            const int64_t es = j0 + jj;
+            const int64_t tslot = e_src_first ? g.rev[es] : es;
+            const uint64_t *er = et.val + (tslot * T + lt) * et.C;
+            for (int co = 0; co < C; co++) {
+              const uint32_t Rp = spread2(s_um[co], cu, cw);
+              if (!((Rp >> cv) & 1u)) continue;
+              const uint32_t R = Rp & ~(1u << cv);
+              uint64_t sum = 0;
+              uint32_t s1 = R;
+              for (;;) {
+                if (__popc(s1) == ra) {
+                  const uint64_t xa = row[s_rank[squeeze2(s1, cu, cv)]];
+                  if (xa) {
+                    const uint64_t y = er[s_rank[squeeze2(R & ~s1, cv, cw)]];
+                    if (y) add_ck(sum, mul_ck(xa, y, of), of);
+                  }
+                }
+                if (s1 == 0) break;
+                s1 = (s1 - 1) & R;
+              }
+              if (sum) add_ck(acc[co * WAVE + lane], sum, of);
+            }
+          }
+        }
+        if (stop) break;
+      }
+      if (of) ofm |= 1ull << lt;
+      // write the lane's row (w, b) for trial lt: sparse -- every marked row;
+      // dense -- the rows nonzero in some trial (the others stay dead)
+      if (grp.dense) {
+        bool nz = false;
+        if (b >= 0)
+          for (int o = 0; o < C; o++) nz |= acc[o * WAVE + lane] != 0;
+        if (nz) atomicOr(&s_live, 1ull << b);
+        __syncthreads();
+      }
+      if (b >= 0 && (!grp.dense || ((s_live >> b) & 1ull))) {
+        const int64_t id = grp.dense ? w * B + b : (int64_t)obase + __popcll(ob & ((1ull << b) - 1ull));
+        uint64_t *drow = dst.val + (id * T + lt) * C;
+        for (int o = 0; o < C; o++) drow[o] = acc[o * WAVE + lane];
+      }
+    }
+    if (grp.dense) {
+      __syncthreads();
+      if (lane == 0) {
+        dst.mask[w] = s_live;
+        n_ent += __popcll(s_live);
+      }
+    } else if (lane == 0) {
+      n_ent += __popcll(ob);
+    }
+  }
+  flag_trials(ovf, ofm);
+  if (grp.prof) {
+    for (int o = 32; o > 0; o >>= 1) {
+      n_scan += __shfl_xor(n_scan, o);
+      n_rows += __shfl_xor(n_rows, o);
+      n_ent += __shfl_xor(n_ent, o);
+    }
+    if (lane == 0) {
+      atomicAdd((unsigned long long *)&grp.prof[0], (unsigned long long)n_scan);
+      atomicAdd((unsigned long long *)&grp.prof[1], (unsigned long long)n_rows);
+      atomicAdd((unsigned long long *)&grp.prof[2], (unsigned long long)n_ent);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ NodeJoin
@@ -693,22 +911,21 @@ int fgrid(const GroupDev &grp, int64_t per_entry) {
 
 }  // namespace
 
-void launch_level_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, LevelDev L,
-                       hipStream_t st) {
-  int64_t N = (int64_t)grp.B * max_low;
-  hipLaunchKernelGGL(k_mark_init, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((N + BLK - 1) / BLK, 4096))),
-                     dim3(BLK), 0, st, g, grp, lowcnt, max_low, L);
-}
-
 static void compact(const GroupDev &grp, LevelDev L, hipStream_t st) {
-  const int64_t nf = grp.n_lim * (int64_t)grp.B;
   const int64_t nv = grp.n_lim;
   const int nb = (int)((nv + CH - 1) / CH);
-  // the chunk counts live past the end of the list (which holds at most nf entries)
-  uint32_t *bcnt = (uint32_t *)(L.list + nf);
-  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.flag, L.vflag, nv, grp.B, bcnt);
-  hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(BLK), 0, st, bcnt, nb, L.cnt);
-  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.flag, L.vflag, nv, bcnt, grp.B, L.idx, L.list);
+  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.m, nv, L.bcnt);
+  hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(BLK), 0, st, L.bcnt, nb, L.cnt);
+  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.m, nv, L.bcnt, L.base, L.list);
+}
+
+int64_t level_chunks(int64_t n_lim) { return (n_lim + CH - 1) / CH; }
+
+void launch_level_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, LevelDev L,
+                       hipStream_t st) {
+  const int64_t N = (int64_t)grp.B * max_low;
+  hipLaunchKernelGGL(k_mark_init, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((N + BLK - 1) / BLK, 4096))),
+                     dim3(BLK), 0, st, g, grp, lowcnt, max_low, L);
 }
 
 void launch_level_next(const GraphDev &g, const GroupDev &grp, LevelDev Lin, LevelDev Lout, hipStream_t st) {
@@ -718,10 +935,8 @@ void launch_level_next(const GraphDev &g, const GroupDev &grp, LevelDev Lin, Lev
 
 void launch_level_compact(const GroupDev &grp, LevelDev L, hipStream_t st) { compact(grp, L, st); }
 
-void launch_level_reset(const GroupDev &grp, LevelDev L, hipStream_t st) {
-  hipLaunchKernelGGL(k_level_reset, dim3(4096), dim3(BLK), 0, st, grp, L);
-  hipLaunchKernelGGL(k_zero_cnt, dim3(1), dim3(1), 0, st, L.cnt);
-}
+// clear the marks for the next group (the list, base and count are rewritten by the next compaction)
+void launch_level_reset(const GroupDev &grp, LevelDev L, hipStream_t st) { launch_fill_u64(L.m, grp.n_lim, st); }
 
 void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, const uint8_t *colr,
                  LevelDev L, RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st) {
@@ -733,17 +948,25 @@ void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, 
 
 void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
                RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st) {
-  const int TC = grp.T * dst.C;
-  const int gr = grp.dense ? (int)std::max<int64_t>(1, std::min<int64_t>(grp.n_lim * grp.B / 4, 65536)) : 8192;
-  const size_t row = (size_t)2 * TC * 8;  // two accumulator words per slot
-  if (16 * row <= 48 * 1024)
-    hipLaunchKernelGGL(k_ej<16>, dim3(gr), dim3(BLK), 16 * row, st, g, grp, colr, Lin, Lout, a, dst, etab,
-                       e_src_first, ovf, cur_lut());
-  else if (4 * row <= 48 * 1024)
-    hipLaunchKernelGGL(k_ej<64>, dim3(gr), dim3(BLK), 4 * row, st, g, grp, colr, Lin, Lout, a, dst, etab,
-                       e_src_first, ovf, cur_lut());
+  if (dst.C <= VMAX_C && (!etab.val || etab.C <= 256)) {
+    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(grp.n_lim, 32768));
+    const size_t lds = (size_t)WAVE * dst.C * sizeof(uint64_t);
+    if (etab.val)
+      hipLaunchKernelGGL(k_ejv<true>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab,
+                         e_src_first, ovf, cur_lut());
+    else
+      hipLaunchKernelGGL(k_ejv<false>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab,
+                         e_src_first, ovf, cur_lut());
+    return;
+  }
+  const int64_t N = grp.dense ? grp.n_lim * grp.B : (int64_t)1 << 62;
+  const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(N, 32768));
+  const size_t lds = (size_t)2 * grp.T * dst.C * sizeof(uint64_t);
+  if (etab.val)
+    hipLaunchKernelGGL(k_ej<true>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab, e_src_first,
+                       ovf, cur_lut());
   else
-    hipLaunchKernelGGL(k_ej<256>, dim3(gr), dim3(BLK), row, st, g, grp, colr, Lin, Lout, a, dst, etab,
+    hipLaunchKernelGGL(k_ej<false>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab,
                        e_src_first, ovf, cur_lut());
 }
 

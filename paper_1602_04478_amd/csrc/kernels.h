@@ -26,11 +26,11 @@ enum OpKind {
 // entry of (v, b) is v * B + b for every v < n_lim; in sparse mode entries are
 // listed (v * 64 + b) and idx maps (v, b) to its entry or -1.
 struct LevelDev {
-  int32_t *idx;    // [n_lim * B]
-  int64_t *list;   // [entries]
-  uint32_t *cnt;   // number of entries
-  uint8_t *flag;   // [n_lim * B] marks while the level is built
-  uint8_t *vflag;  // [n_lim] per-vertex marks while the level is built
+  uint64_t *m;      // [n_lim] bit b of m[v]: (v, b) is an entry
+  uint32_t *base;   // [n_lim] index of v's first entry (entries numbered in (v, b) order)
+  int64_t *list;    // [entries] v * 64 + b
+  uint32_t *cnt;    // number of entries
+  uint32_t *bcnt;   // [chunks] compaction scratch
 };
 
 // A frontier register: one row of T * C slots per entry of its level.
@@ -75,7 +75,9 @@ struct AccDev {
 };
 
 const uint16_t *lut_device(int device);
-inline int max_row_slots() { return 6144; }  // trials x slots of one frontier row (EdgeJoin LDS)  // colex rank / unrank tables
+// trials x slots of one frontier row: EdgeJoin keeps two accumulator words per
+// slot in LDS, within 64 KiB per workgroup with its rank tables
+inline int max_row_slots() { return 3584; }
 
 void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0, int T, uint8_t *out,
                    hipStream_t st);
@@ -90,6 +92,7 @@ void launch_level_init(const GraphDev &g, const GroupDev &grp, const int32_t *lo
 void launch_level_next(const GraphDev &g, const GroupDev &grp, LevelDev Lin, LevelDev Lout, hipStream_t st);
 void launch_level_compact(const GroupDev &grp, LevelDev L, hipStream_t st);
 void launch_level_reset(const GroupDev &grp, LevelDev L, hipStream_t st);
+int64_t level_chunks(int64_t n_lim);  // size of LevelDev::bcnt
 void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, const uint8_t *colr,
                  LevelDev L, RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st);
 void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
