@@ -166,17 +166,35 @@ cc_status cc_count_colors(cc_graph g, cc_query q, int32_t trials, const uint8_t 
 
 /*
  * Batched form: nq queries on one graph, query i with trials[i] colourings
- * from seeds[i].  All colourings of all queries are solved together: trials
- * form the batch dimension of every launch and the launch sequence is
- * captured once in a hipGraph and replayed (tuning->use_graphs).
+ * from seeds[i] (trial t of query i uses the colouring (seeds[i], t) of the
+ * contract, so the counts equal cc_count's).  The colourings of a query are
+ * solved in trial groups that form the batch dimension of every launch; the
+ * launch sequence of a trial group is captured once in a hipGraph and
+ * replayed for the next groups (use_graphs).
  *   counts / overflow  host, concatenated per query in order (sum of trials[i]).
  *   estimates          host, double[nq] or NULL.
- *   tuning             NULL for automatic choices.
+ *   tuning             NULL: the trial-group size is tuned online on the
+ *                      query's first trials (see cc_last_tune_report) and
+ *                      graphs are used; else the given choices.
  * Errors: as cc_count.
  */
 cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint64_t *seeds,
                          const int32_t *trials, uint64_t *counts, uint8_t *overflow, double *estimates,
                          const cc_tuning *tuning, void *stream);
+
+/*
+ * What the calling thread's last cc_count_batch chose for its last query
+ * (online tuning when `tuning` was NULL): the trial-group size, the sizes
+ * timed and their seconds per colouring, and the number of graph replays.
+ */
+typedef struct {
+  int32_t trial_group;
+  int32_t candidates;
+  int32_t tried_trial_group[8];
+  double tried_seconds_per_colouring[8];
+  uint64_t graph_replays;
+} cc_tune_report;
+cc_status cc_last_tune_report(cc_tune_report *out);
 
 /* ------------------------------------------------------------------ serving */
 

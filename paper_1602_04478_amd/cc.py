@@ -21,8 +21,8 @@ STATUS = {0: "CC_OK", 1: "CC_E_ARG", 2: "CC_E_GRAPH", 3: "CC_E_QUERY_TW", 4: "CC
 EXPORTS = ["cc_graph_create", "cc_graph_destroy", "cc_graph_info", "cc_query_create", "cc_query_destroy",
            "cc_query_info", "cc_query_plan", "cc_footprint", "cc_colors", "cc_count", "cc_count_colors",
            "cc_count_batch", "cc_server_create", "cc_server_add_graph", "cc_server_submit", "cc_server_poll",
-           "cc_server_drain", "cc_server_destroy", "cc_profile_enable", "cc_profile_read", "cc_status_str",
-           "cc_last_error"]
+           "cc_server_drain", "cc_server_destroy", "cc_last_tune_report", "cc_profile_enable", "cc_profile_read",
+           "cc_status_str", "cc_last_error"]
 
 
 class CCError(RuntimeError):
@@ -243,6 +243,21 @@ def count_batch(g: Graph, queries, seeds, trials, tuning: dict | None = None, st
     _check(lib().cc_count_batch(g.h, nq, qs, _ptr(sd), _ptr(tr), _ptr(counts), _ptr(ovf), _ptr(est),
                                 ctypes.byref(tun) if tun else None, stream))
     return counts, ovf, est
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("trial_group", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("tried_trial_group", ctypes.c_int32 * 8), ("tried_seconds_per_colouring", ctypes.c_double * 8),
+                ("graph_replays", ctypes.c_uint64)]
+
+
+def last_tune_report() -> dict:
+    """What the calling thread's last count_batch chose (cc_last_tune_report)."""
+    r = TuneReport()
+    _check(lib().cc_last_tune_report(ctypes.byref(r)))
+    n = min(r.candidates, 8)
+    return {"trial_group": r.trial_group, "graph_replays": int(r.graph_replays),
+            "tried": [(r.tried_trial_group[i], r.tried_seconds_per_colouring[i]) for i in range(n)]}
 
 
 class Server:

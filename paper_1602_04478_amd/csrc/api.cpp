@@ -125,6 +125,7 @@ cc_status cc_query_create(int32_t k, int32_t num_edges, const int32_t *edges, cc
     auto q = new cc_query_s;
     try {
       q->plan = cc::make_plan(k, e);
+      if (const char *vb = getenv("CC_VERBOSE"); vb && *vb == '1') cc::dump_programs(q->plan);
     } catch (...) {
       delete q;
       throw;
@@ -215,15 +216,28 @@ cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint6
       cc::fail(CC_E_ARG, "bad argument");
     size_t off = 0;
     cc::ExecOptions o = opts_from(tuning);
-    for (int i = 0; i < nq; i++) {
+    for (int i = 0; i < nq; i++)
       if (!qs[i] || trials[i] < 1) cc::fail(CC_E_ARG, "bad query or trial count");
-      cc::ColourSource cs;
-      cs.seed = seeds[i];
-      auto r = cc::run_count(*g->g, qs[i]->plan, trials[i], cs, o, (hipStream_t)stream, nullptr);
+    for (int i = 0; i < nq; i++) {
+      auto r = cc::run_batched(*g->g, qs[i]->plan, trials[i], seeds[i], tuning ? &o : nullptr, (hipStream_t)stream);
       write_results(qs[i]->plan, r, trials[i], counts + off, overflow + off, nullptr,
                     estimates ? estimates + i : nullptr);
       off += trials[i];
     }
+  });
+}
+
+cc_status cc_last_tune_report(cc_tune_report *out) {
+  return guard([&] {
+    if (!out) cc::fail(CC_E_ARG, "null output");
+    cc::TuneReport r = cc::last_tune();
+    out->trial_group = r.trial_group;
+    out->candidates = r.candidates;
+    for (int i = 0; i < 8; i++) {
+      out->tried_trial_group[i] = r.tried_T[i];
+      out->tried_seconds_per_colouring[i] = r.tried_sec_per_colouring[i];
+    }
+    out->graph_replays = r.replays;
   });
 }
 

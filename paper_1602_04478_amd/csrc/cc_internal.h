@@ -148,6 +148,19 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
 
 uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt);
 
+// All trials of one query with captured launch sequences replayed per trial
+// group; `tuning` null = tune the trial-group size online.
+struct TuneReport {
+  int trial_group = 0;     // chosen
+  int candidates = 0;      // trial-group sizes timed
+  int tried_T[8] = {0};
+  double tried_sec_per_colouring[8] = {0};
+  uint64_t replays = 0;    // graph replays by the chosen solver
+};
+CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t seed, const ExecOptions *tuning,
+                        hipStream_t stream);
+TuneReport last_tune();  // of the calling thread's last run_batched
+
 // Device colouring (rank order) for one trial, copied to host by original id.
 void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t stream);
 
@@ -159,6 +172,7 @@ struct KernelProfile {
   uint64_t work[3];
 };
 std::vector<KernelProfile> profile_read();
+void dump_programs(const Plan &p);  // the cycle programs, to stderr
 
 double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf);
 

@@ -13,6 +13,8 @@
 // potential entry and the EdgeJoin pulls over all vertices; the rest run in
 // sparse groups, whose registers keep lists of their live entries.
 #include <algorithm>
+#include <chrono>
+#include <memory>
 #include <array>
 #include <functional>
 #include <cmath>
@@ -52,6 +54,20 @@ struct DevMem {
   ~DevMem() { release(); }
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
+  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevMem &operator=(DevMem &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   template <typename T>
   T *as() const {
     return (T *)p;
@@ -260,6 +276,20 @@ std::vector<KernelProfile> profile_read() {
   return v;
 }
 
+void dump_programs(const Plan &p) {
+    static const char *kn[] = {"INIT", "NJ", "EJ", "AXPY", "MROOT", "MU", "MV", "MEDGE", "MEDGE_T"};
+    for (size_t bi = 0; bi < p.programs.size(); bi++) {
+      const Program &P = p.programs[bi];
+      if (P.ops.empty()) continue;
+      fprintf(stderr, "[cc] block %zu program: %zu ops, %zu registers, depth %d\n", bi, P.ops.size(), P.reg_s.size(),
+              P.max_depth);
+      for (auto &o : P.ops)
+        fprintf(stderr, "[cc]   %-7s dst=%d(s%d,d%d) a=%d b=%d tab=%d ntab=%d w=%llu first=%d\n", kn[o.kind], o.dst,
+                o.dst >= 0 ? P.reg_s[o.dst] : -1, o.dst >= 0 ? P.reg_depth[o.dst] : -1, o.a, o.b, o.tab, o.ntab,
+                (unsigned long long)o.w, o.first);
+    }
+}
+
 uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt) {
   int T = std::min(std::max(trials, 1), 64);
   if (opt.trial_group > 0) T = std::min(T, opt.trial_group);
@@ -308,384 +338,621 @@ double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::v
   return (double)(num / den);
 }
 
-// ------------------------------------------------------------------ main
-CountResult run_count(const DevGraph &g, const Plan &p, int trials, const ColourSource &cs, const ExecOptions &opt,
-                      hipStream_t st, std::vector<u128> *per_source) {
+// ------------------------------------------------------------------ solver
+//
+// A Solver holds everything one (graph, plan, trial-group size) needs on the
+// device: colours, child tables, frontier registers, levels, the one-workgroup
+// tier's program and its scratch.  After the first trial group -- which learns
+// which sources the one-workgroup tier hands back (that depends only on the
+// graph and the program) -- the launch sequence of a trial group is fixed:
+// no allocation, no host synchronisation, every clear a kernel.  It can then
+// be captured once in a hipGraph and replayed per trial group, the seed and
+// first trial read from device memory.
+class Solver {
+ public:
+  Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt, hipStream_t st);
+  ~Solver();
+  // trials [t0, t0 + Tg) into res (and per_source, indexed [t][orig id])
+  void run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountResult &res, std::vector<u128> *per_source);
+  int T() const { return z_.T; }
+  uint64_t graph_replays = 0;
+
+ private:
+  struct Grp {
+    const int32_t *dsrc;  // device sources of the group
+    const int32_t *hsrc;  // host copy
+    int64_t B;
+    bool dense;
+  };
+  struct Light {  // one cycle block's one-workgroup tier
+    bool probed = false;
+    std::vector<int32_t> src;    // sources it runs
+    std::vector<int32_t> fails;  // sources it hands back (descending), run as groups
+    DevMem d_ops, d_rd, d_rC, d_rs, d_tv, d_ctr, d_fail, d_src, d_fails;
+    LightArgs la{};
+    int grid = 0;
+  };
+  void enqueue(int Tg, bool seed_dev, bool probe, Profiler *prof);
+  void enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof);
+  void run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof);
+  TabDev tabdev(int blk) const {
+    TabDev t{nullptr, 0, 0};
+    if (blk >= 0) {
+      t.val = tabs_[blk].as<uint64_t>();
+      t.C = table_C(p_, blk);
+      t.s = p_.blocks[blk].size;
+    }
+    return t;
+  }
+  LevelDev leveldev(int d) {
+    LevelDev L;
+    L.m = levels_[d].m.as<uint64_t>();
+    L.base = levels_[d].base.as<uint32_t>();
+    L.list = levels_[d].list.as<int64_t>();
+    L.cnt = levels_[d].cnt.as<uint32_t>();
+    L.bcnt = levels_[d].bcnt.as<uint32_t>();
+    return L;
+  }
+
+  const DevGraph &g_;
+  const Plan &p_;
+  ExecOptions opt_;
+  hipStream_t st_;
+  Sizing z_{};
+  GraphDev gd_{};
+  std::vector<int32_t> sources_;
+  int64_t ndense_ = 0;
+  bool use_light_ = true, fallback_dense_ = false;
+  int64_t light_scratch_ = 2 << 20;
+  int64_t nlim_max_ = 1;
+  DevMem d_src_, d_col_, d_sum_, d_ovf_, d_per_, d_hcol_, d_param_;
+  bool per_alloc_ = false;
+  std::vector<DevMem> tabs_;
+  std::vector<RegBuf> regs_;
+  std::vector<LevelBuf> levels_;
+  std::vector<Light> light_;
+  DevMem light_scratch_buf_;
+  AccDev acc_{};
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t exec_ = nullptr;
+  int exec_T_ = 0;
+  hipStream_t own_st_ = nullptr;
+};
+
+Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt, hipStream_t st)
+    : g_(g), p_(p), opt_(opt), st_(st) {
   if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
   HIP_CHECK(hipSetDevice(g.device));
+  if (!st_) {  // the null stream cannot be captured: work on a stream of our own
+    HIP_CHECK(hipStreamCreate(&own_st_));
+    st_ = own_st_;
+    st = st_;
+  }
   const int k = p.k;
   uint64_t budget = opt.mem_budget ? opt.mem_budget : (uint64_t)(free_bytes() * 0.85);
-  Sizing z = choose(g, p, trials, opt, budget);
-  const int T = z.T;
-
-  CountResult res;
-  res.exact.assign(trials, 0);
-  res.overflow.assign(trials, 0);
-  if (per_source) per_source->assign((size_t)trials * g.n, 0);
-
-  GraphDev gd{g.rp, g.col, g.rev, g.n, g.m2};
+  z_ = choose(g, p, trials, opt, budget);
+  const int T = z_.T;
+  gd_ = GraphDev{g.rp, g.col, g.rev, g.n, g.m2};
 
   // sources: lowcnt >= 2, descending rank
-  std::vector<int32_t> sources;
   for (int64_t r = g.n - 1; r >= 0; r--)
-    if (g.h_lowcnt[r] >= 2) sources.push_back((int32_t)r);
+    if (g.h_lowcnt[r] >= 2) sources_.push_back((int32_t)r);
   // dense cut: sources whose two-step reach covers a good part of their prefix
-  int64_t ndense = 0;
-  for (size_t i = 0; i < sources.size(); i++) {
-    int64_t u = sources[i];
-    if (g.h_r2[u] * 16 >= u && u > 4096) ndense = (int64_t)i + 1;
+  for (size_t i = 0; i < sources_.size(); i++) {
+    int64_t u = sources_[i];
+    if (g.h_r2[u] * 16 >= u && u > 4096) ndense_ = (int64_t)i + 1;
     else break;
   }
   // CC_DENSE=all / none overrides the choice (used to exercise both paths)
-  bool force_sparse = false;
   if (const char *ev = getenv("CC_DENSE")) {
-    if (!strcmp(ev, "all")) ndense = (int64_t)sources.size();
-    if (!strcmp(ev, "none")) {
-      ndense = 0;
-      force_sparse = true;
-    }
+    if (!strcmp(ev, "all")) ndense_ = (int64_t)sources_.size();
+    if (!strcmp(ev, "none")) ndense_ = 0;
   }
-  bool use_light = true;
   if (const char *ev = getenv("CC_LIGHT"))
-    if (!strcmp(ev, "0")) use_light = false;
-  int64_t light_scratch = 2 << 20;
-  if (const char *ev = getenv("CC_LIGHT_SCRATCH")) light_scratch = std::max<int64_t>(4096, atoll(ev));
-  int Bmax = std::max(z.B_dense, z.B_sparse);
-  int64_t nlim_max = sources.empty() ? 1 : sources[0];
-  if (nlim_max < 1) nlim_max = 1;
+    if (!strcmp(ev, "0")) use_light_ = false;
+  if (const char *ev = getenv("CC_LIGHT_SCRATCH")) light_scratch_ = std::max<int64_t>(4096, atoll(ev));
+  if (const char *ev = getenv("CC_FALLBACK"))
+    if (!strcmp(ev, "dense")) fallback_dense_ = true;
+  const int Bmax = std::max(z_.B_dense, z_.B_sparse);
+  nlim_max_ = sources_.empty() ? 1 : std::max<int64_t>(1, sources_[0]);
 
-  DevMem d_src(sizeof(int32_t) * std::max<size_t>(1, sources.size()));
-  if (!sources.empty())
-    HIP_CHECK(hipMemcpyAsync(d_src.p, sources.data(), sizeof(int32_t) * sources.size(), hipMemcpyHostToDevice, st));
-  DevMem d_col((size_t)g.n * T);
-  DevMem d_sum(sizeof(uint64_t) * 2 * 64), d_ovf(sizeof(uint32_t) * 64);
-  DevMem d_per(per_source ? sizeof(uint64_t) * 2 * (size_t)g.n * T : 8);
-  DevMem d_hcol;
-  if (!cs.from_seed) d_hcol.alloc((size_t)g.n * T);
+  d_src_.alloc(sizeof(int32_t) * std::max<size_t>(1, sources_.size()));
+  if (!sources_.empty())
+    HIP_CHECK(hipMemcpyAsync(d_src_.p, sources_.data(), sizeof(int32_t) * sources_.size(), hipMemcpyHostToDevice, st));
+  d_col_.alloc((size_t)g.n * T);
+  d_sum_.alloc(sizeof(uint64_t) * 2 * 64);
+  d_ovf_.alloc(sizeof(uint32_t) * 64);
+  d_per_.alloc(8);
+  d_param_.alloc(sizeof(uint64_t) * 2);
+  acc_ = AccDev{d_sum_.as<uint64_t>(), d_ovf_.as<uint32_t>(), nullptr};
 
   // child tables
-  std::vector<DevMem> tabs(p.blocks.size());
+  tabs_.resize(p.blocks.size());
   for (size_t i = 0; i < p.blocks.size(); i++) {
     const PBlock &B = p.blocks[i];
     if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE) continue;
     int64_t keys = is_edge_table(p, (int)i) ? g.m2 : g.n;
-    tabs[i].alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, keys) * T * table_C(p, (int)i));
+    tabs_[i].alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, keys) * T * table_C(p, (int)i));
   }
-  auto tabdev = [&](int blk) {
-    TabDev t{nullptr, 0, 0};
-    if (blk >= 0) {
-      t.val = tabs[blk].as<uint64_t>();
-      t.C = table_C(p, blk);
-      t.s = p.blocks[blk].size;
-    }
-    return t;
-  };
-
   // registers and levels: pools sized for the largest program
   size_t nregs = 0;
   int dmax = 1;
+  std::vector<int> reg_smax;
   for (auto &P : p.programs) {
     nregs = std::max(nregs, P.reg_s.size());
     dmax = std::max(dmax, P.max_depth);
+    if (reg_smax.size() < P.reg_s.size()) reg_smax.resize(P.reg_s.size(), 0);
+    for (size_t r = 0; r < P.reg_s.size(); r++) reg_smax[r] = std::max(reg_smax[r], (int)slots_pair(k, P.reg_s[r]));
   }
-  std::vector<RegBuf> regs(nregs);
-  auto ensure_reg = [&](int r, int s) {
-    RegBuf &R = regs[r];
-    int C = (int)slots_pair(k, s);
-    size_t vb = sizeof(uint64_t) * (size_t)nlim_max * Bmax * T * C;
-    if (R.val.bytes < vb) R.val.alloc(vb);
-    if (R.mask.bytes < sizeof(uint64_t) * (size_t)nlim_max) R.mask.alloc(sizeof(uint64_t) * (size_t)nlim_max);
-  };
-  std::vector<LevelBuf> levels(dmax + 2);
-  const size_t nf_max = (size_t)nlim_max * Bmax;
-  auto ensure_level = [&](int d) {
-    LevelBuf &L = levels[d];
-    if (L.m.bytes >= sizeof(uint64_t) * (size_t)nlim_max) return;
-    L.m.alloc(sizeof(uint64_t) * (size_t)nlim_max);
-    launch_fill_u64(L.m.as<uint64_t>(), nlim_max, st);
-    L.base.alloc(sizeof(uint32_t) * (size_t)nlim_max);
+  regs_.resize(nregs);
+  for (size_t r = 0; r < nregs; r++) {
+    regs_[r].val.alloc(sizeof(uint64_t) * (size_t)nlim_max_ * Bmax * T * reg_smax[r]);
+    regs_[r].mask.alloc(sizeof(uint64_t) * (size_t)nlim_max_);
+  }
+  levels_.resize(dmax + 2);
+  const size_t nf_max = (size_t)nlim_max_ * Bmax;
+  for (int d = 1; d <= dmax; d++) {
+    LevelBuf &L = levels_[d];
+    L.m.alloc(sizeof(uint64_t) * (size_t)nlim_max_);
+    launch_fill_u64(L.m.as<uint64_t>(), nlim_max_, st);
+    L.base.alloc(sizeof(uint32_t) * (size_t)nlim_max_);
     L.list.alloc(sizeof(int64_t) * nf_max);
     L.cnt.alloc(sizeof(uint32_t));
-    L.bcnt.alloc(sizeof(uint32_t) * (size_t)level_chunks(nlim_max));
-  };
-  auto leveldev = [&](int d) {
-    LevelDev L;
-    L.m = levels[d].m.as<uint64_t>();
-    L.base = levels[d].base.as<uint32_t>();
-    L.list = levels[d].list.as<int64_t>();
-    L.cnt = levels[d].cnt.as<uint32_t>();
-    L.bcnt = levels[d].bcnt.as<uint32_t>();
-    return L;
-  };
-
-  const int32_t *lowcnt_d = g.lowcnt;
-  Profiler prof(st);
-  DevMem light_scratch_buf;
-  int64_t light_handled = 0;
-
-  for (int t0 = 0; t0 < trials; t0 += T) {
-    int Tg = std::min(T, trials - t0);
-    // colours of this trial group, rank order
-    if (cs.from_seed) {
-      launch_colour(g.orig, g.n, k, cs.seed, t0, Tg, d_col.as<uint8_t>(), st);
-    } else {
-      HIP_CHECK(hipMemcpyAsync(d_hcol.p, cs.host + (size_t)t0 * g.n, (size_t)g.n * Tg, hipMemcpyHostToDevice, st));
-      launch_permute_colours(d_hcol.as<uint8_t>(), g.orig, g.n, Tg, d_col.as<uint8_t>(), st);
-    }
-    const uint8_t *colr = d_col.as<uint8_t>();
-    HIP_CHECK(hipMemsetAsync(d_sum.p, 0, d_sum.bytes, st));
-    HIP_CHECK(hipMemsetAsync(d_ovf.p, 0, d_ovf.bytes, st));
-    if (per_source) HIP_CHECK(hipMemsetAsync(d_per.p, 0, d_per.bytes, st));
-    AccDev acc{d_sum.as<uint64_t>(), d_ovf.as<uint32_t>(), per_source ? d_per.as<uint64_t>() : nullptr};
-    uint32_t *ovf = d_ovf.as<uint32_t>();
-
-    for (size_t bi = 0; bi < p.blocks.size(); bi++) {
-      const PBlock &B = p.blocks[bi];
-      if (B.kind == BK_LEAF) {
-        int a = B.nodes[0];
-        (void)a;
-        int ec = B.edge_child[0];
-        launch_leaf(gd, Tg, k, colr, tabdev(B.node_child[0]), tabdev(ec), ec >= 0 ? B.edge_first_lo[0] : 0,
-                    tabdev(B.node_child[1]), tabs[bi].as<uint64_t>(), B.size, table_C(p, (int)bi), ovf, st);
-        HIP_CHECK(hipGetLastError());
-        continue;
-      }
-      if (B.kind == BK_ROOT_SINGLE) {
-        TabDev u = tabdev(B.single_child);
-        launch_root_single(g.n, Tg, u, acc, st);
-        HIP_CHECK(hipGetLastError());
-        continue;
-      }
-      // cycle block
-      const Program &P = p.programs[bi];
-      uint64_t *out = nullptr;
-      int C_out = 0;
-      if (B.kind == BK_CYCLE) {
-        out = tabs[bi].as<uint64_t>();
-        C_out = table_C(p, (int)bi);
-        int64_t keys = is_edge_table(p, (int)bi) ? g.m2 : g.n;
-        launch_fill_u64(out, keys * Tg * C_out, st);
-      }
-      for (size_t r = 0; r < P.reg_s.size(); r++) ensure_reg((int)r, P.reg_s[r]);
-      for (int d = 1; d <= P.max_depth; d++) ensure_level(d);
-      // NodeJoin outputs keep their input's activity mask
-      std::vector<int> mown(P.reg_s.size());
-      for (size_t r = 0; r < mown.size(); r++) mown[r] = (int)r;
-      for (auto &op : P.ops)
-        if (op.kind == OP_NJ) mown[op.dst] = mown[op.a];
-      auto regdev = [&](int r) {
-        RegDev d;
-        d.val = regs[r].val.as<uint64_t>();
-        d.mask = regs[mown[r]].mask.as<uint64_t>();
-        d.C = (int)slots_pair(k, P.reg_s[r]);
-        d.s = P.reg_s[r];
-        return d;
-      };
-      auto lv = [&](int r) { return leveldev(P.reg_depth[r]); };
-      struct Grp {
-        const int32_t *dsrc;          // device sources of the group
-        const int32_t *hsrc;          // host copy
-        int64_t B;
-        bool dense;
-      };
-      auto run_group = [&](const Grp &G) {
-        GroupDev grp;
-        grp.src = G.dsrc;
-        grp.B = (int)G.B;
-        grp.T = Tg;
-        grp.k = k;
-        grp.n_lim = G.hsrc[0];
-        grp.dense = G.dense ? 1 : 0;
-        grp.prof = nullptr;
-        int max_low = 0;
-        for (int64_t i = 0; i < G.B; i++) max_low = std::max(max_low, g.h_lowcnt[G.hsrc[i]]);
-        std::vector<char> built(P.max_depth + 2, 0);
-        std::function<void(int)> build = [&](int d) {  // sparse groups: entries of depth d
-          if (G.dense || built[d]) return;
-          prof.begin("level_build_sparse", false, 0, 0, 0);
-          if (d == 1) {
-            launch_level_init(gd, grp, lowcnt_d, max_low, leveldev(1), st);
-            launch_level_compact(grp, leveldev(1), st);
-          } else {
-            build(d - 1);
-            launch_level_next(gd, grp, leveldev(d - 1), leveldev(d), st);
-          }
-          HIP_CHECK(hipGetLastError());
-          prof.end();
-          built[d] = 1;
-        };
-        for (size_t oi = 0; oi < P.ops.size(); oi++) {
-          const Op &op = P.ops[oi];
-          static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
-                                        "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
-          std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
-          if (op.kind == OP_INIT) build(1);
-          if (op.kind == OP_EJ) build(P.reg_depth[op.dst]);
-          if (op.kind == OP_EJ) {
-            // algorithmic bytes: a 4-byte neighbour id per scanned pair, an
-            // input row (plus the annotated edge's table row) per relaxation,
-            // an output row per entry
-            const double Cin = (double)slots_pair(k, P.reg_s[op.a]), Cout = (double)slots_pair(k, P.reg_s[op.dst]);
-            const double Ce = op.tab >= 0 ? (double)table_C(p, op.tab) : 0.0;
-            grp.prof = prof.begin(nm.c_str(), true, 4.0, 8.0 * (Cin + Ce), 8.0 * Tg * Cout);
-          } else {
-            grp.prof = nullptr;
-            prof.begin(nm.c_str(), false, 0, 0, 0);
-          }
-          switch (op.kind) {
-            case OP_INIT: {
-              RegDev d = regdev(op.dst);
-              if (G.dense) {
-                launch_fill_u64(d.val, grp.n_lim * grp.B * (int64_t)Tg * d.C, st);
-                launch_fill_u64(d.mask, grp.n_lim, st);
-              }
-              launch_init(gd, grp, lowcnt_d, max_low, colr, lv(op.dst), d, tabdev(op.tab), op.tab_src_first,
-                          tabdev(op.ntab), ovf, st);
-              break;
-            }
-            case OP_NJ:
-              launch_nj(gd, grp, colr, lv(op.a), regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
-              break;
-            case OP_EJ:
-              launch_ej(gd, grp, colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst), tabdev(op.tab),
-                        op.tab_src_first, ovf, st);
-              break;
-            case OP_AXPY:
-              launch_axpy(grp, lv(op.a), regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
-              break;
-            case OP_MROOT:
-              launch_mroot(grp, g.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w, acc, st);
-              break;
-            case OP_MU:
-            case OP_MV:
-              launch_munary(grp, g.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w,
-                            op.kind == OP_MU, out, op.s, C_out, ovf, st);
-              break;
-            case OP_MEDGE:
-              launch_medge(gd, grp, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), tabdev(op.tab),
-                           op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
-              break;
-            case OP_MEDGE_T:
-              launch_medge_t(gd, grp, colr, lowcnt_d, max_low, tabdev(op.ntab), lv(op.b), regdev(op.b),
-                             tabdev(op.tab), op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
-              break;
-          }
-          HIP_CHECK(hipGetLastError());
-          prof.end();
-        }
-        for (int d = 1; d <= P.max_depth; d++)
-          if (built[d]) launch_level_reset(grp, leveldev(d), st);
-      };
-      // 1. dense groups: the sources with the widest reach
-      for (int64_t i = 0; i < ndense; i += z.B_dense)
-        run_group({d_src.as<int32_t>() + i, sources.data() + i, std::min<int64_t>(z.B_dense, ndense - i), true});
-      // 2. one workgroup per source for the rest; 3. grouped sparse path for what does not fit
-      std::vector<int32_t> rest(sources.begin() + ndense, sources.end());
-      const int64_t nrest = (int64_t)rest.size();
-      bool light_ok = use_light && nrest > 0 && P.max_depth <= light_max_depth() &&
-                      (int)P.reg_s.size() <= light_max_regs();
-      if (light_ok) {
-        std::vector<LOp> lops;
-        for (auto &o : P.ops)
-          lops.push_back({(int)o.kind, o.dst, o.a, o.b, o.tab, o.tab_src_first, o.ntab, o.s, o.first, o.swapped,
-                          o.w});
-        std::vector<int32_t> rd(P.reg_s.size()), rC(P.reg_s.size()), rs(P.reg_s.size());
-        for (size_t r = 0; r < P.reg_s.size(); r++) {
-          rd[r] = P.reg_depth[r];
-          rC[r] = (int32_t)slots_pair(k, P.reg_s[r]);
-          rs[r] = P.reg_s[r];
-        }
-        std::vector<TabDev> tv(p.blocks.size());
-        for (size_t b2 = 0; b2 < p.blocks.size(); b2++) tv[b2] = tabdev(tabs[b2].p ? (int)b2 : -1);
-        DevMem d_ops(sizeof(LOp) * lops.size()), d_rd(4 * rd.size()), d_rC(4 * rC.size()), d_rs(4 * rs.size());
-        DevMem d_tv(sizeof(TabDev) * tv.size()), d_ctr(8), d_fail(4 * nrest);
-        HIP_CHECK(hipMemcpyAsync(d_ops.p, lops.data(), sizeof(LOp) * lops.size(), hipMemcpyHostToDevice, st));
-        HIP_CHECK(hipMemcpyAsync(d_rd.p, rd.data(), 4 * rd.size(), hipMemcpyHostToDevice, st));
-        HIP_CHECK(hipMemcpyAsync(d_rC.p, rC.data(), 4 * rC.size(), hipMemcpyHostToDevice, st));
-        HIP_CHECK(hipMemcpyAsync(d_rs.p, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st));
-        HIP_CHECK(hipMemcpyAsync(d_tv.p, tv.data(), sizeof(TabDev) * tv.size(), hipMemcpyHostToDevice, st));
-        HIP_CHECK(hipMemsetAsync(d_ctr.p, 0, 8, st));
-        int ncu = 0;
-        HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g.device));
-        int grid = std::max(1, ncu) * 3;
-        if (light_scratch_buf.bytes < (size_t)light_scratch * grid) light_scratch_buf.alloc((size_t)light_scratch * grid);
-        DevMem d_rest(4 * nrest);
-        HIP_CHECK(hipMemcpyAsync(d_rest.p, rest.data(), 4 * nrest, hipMemcpyHostToDevice, st));
-        LightArgs la;
-        la.g = gd;
-        la.lowcnt = lowcnt_d;
-        la.colr = colr;
-        la.T = Tg;
-        la.k = k;
-        la.src = d_rest.as<int32_t>();
-        la.nsrc = (int)nrest;
-        la.next = d_ctr.as<uint32_t>();
-        la.fail = d_fail.as<int32_t>();
-        la.nfail = d_ctr.as<uint32_t>() + 1;
-        la.ops = d_ops.as<LOp>();
-        la.nops = (int)lops.size();
-        la.reg_depth = d_rd.as<int32_t>();
-        la.reg_C = d_rC.as<int32_t>();
-        la.reg_s = d_rs.as<int32_t>();
-        la.nregs = (int)rd.size();
-        la.D = P.max_depth;
-        la.tabs = d_tv.as<TabDev>();
-        la.out = out;
-        la.s_out = B.size;
-        la.C_out = C_out;
-        la.acc = acc;
-        la.scratch = light_scratch_buf.as<uint8_t>();
-        la.scratch_per_wg = light_scratch;
-        la.lut = lut_device(g.device);
-        prof.begin("light", false, 0, 0, 0);
-        launch_light(la, grid, st);
-        HIP_CHECK(hipGetLastError());
-        prof.end();
-        uint32_t hc[2];
-        HIP_CHECK(hipMemcpyAsync(hc, d_ctr.p, 8, hipMemcpyDeviceToHost, st));
-        HIP_CHECK(hipStreamSynchronize(st));
-        rest.resize(hc[1]);
-        if (hc[1]) HIP_CHECK(hipMemcpy(rest.data(), d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost));
-        std::sort(rest.begin(), rest.end(), std::greater<int32_t>());
-        light_handled += nrest - (int64_t)hc[1];
-      }
-      if (!rest.empty()) {
-        DevMem d_f(4 * rest.size());
-        HIP_CHECK(hipMemcpyAsync(d_f.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
-        // what the one-workgroup path handed back has wide reach: dense groups,
-        // unless every path is forced sparse
-        bool fdense = false;
-        if (const char *ev = getenv("CC_FALLBACK"))
-          if (!strcmp(ev, "dense")) fdense = true;
-        for (int64_t i = 0; i < (int64_t)rest.size(); i += z.B_sparse)
-          run_group({d_f.as<int32_t>() + i, rest.data() + i, std::min<int64_t>(z.B_sparse, (int64_t)rest.size() - i),
-                     fdense});
-        HIP_CHECK(hipStreamSynchronize(st));
-      }
-    }
-    // results of this trial group
-    std::vector<uint64_t> hs(2 * 64);
-    std::vector<uint32_t> ho(64);
-    HIP_CHECK(hipMemcpyAsync(hs.data(), d_sum.p, sizeof(uint64_t) * 2 * 64, hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipMemcpyAsync(ho.data(), d_ovf.p, sizeof(uint32_t) * 64, hipMemcpyDeviceToHost, st));
-    std::vector<uint64_t> hp;
-    if (per_source) {
-      hp.resize(2 * (size_t)g.n * Tg);
-      HIP_CHECK(hipMemcpyAsync(hp.data(), d_per.p, sizeof(uint64_t) * hp.size(), hipMemcpyDeviceToHost, st));
-    }
-    HIP_CHECK(hipStreamSynchronize(st));
-    prof.finish();
-    for (int t = 0; t < Tg; t++) {
-      res.exact[t0 + t] = (u128)hs[2 * t] | ((u128)hs[2 * t + 1] << 64);
-      res.overflow[t0 + t] = ho[t] ? 1 : 0;
-    }
-    if (per_source)
-      for (int64_t r = 0; r < g.n; r++)
-        for (int t = 0; t < Tg; t++) {
-          size_t i = 2 * ((size_t)r * Tg + t);
-          (*per_source)[(size_t)(t0 + t) * g.n + g.h_orig[r]] = (u128)hp[i] | ((u128)hp[i + 1] << 64);
-        }
+    L.bcnt.alloc(sizeof(uint32_t) * (size_t)level_chunks(nlim_max_));
   }
+  // one-workgroup tier per cycle block
+  light_.resize(p.blocks.size());
+  int ncu = 0;
+  HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g.device));
+  std::vector<int32_t> rest(sources_.begin() + ndense_, sources_.end());
+  for (size_t bi = 0; bi < p.blocks.size(); bi++) {
+    const PBlock &B = p.blocks[bi];
+    Light &L = light_[bi];
+    if (B.kind != BK_CYCLE && B.kind != BK_ROOT_CYCLE) {
+      L.probed = true;
+      continue;
+    }
+    const Program &P = p.programs[bi];
+    const bool ok = use_light_ && !rest.empty() && P.max_depth <= light_max_depth() &&
+                    (int)P.reg_s.size() <= light_max_regs();
+    if (!ok) {
+      L.probed = true;
+      L.fails = rest;
+      if (!rest.empty()) {
+        L.d_fails.alloc(4 * rest.size());
+        HIP_CHECK(hipMemcpyAsync(L.d_fails.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
+      }
+      continue;
+    }
+    L.src = rest;
+    std::vector<LOp> lops;
+    for (auto &o : P.ops)
+      lops.push_back({(int)o.kind, o.dst, o.a, o.b, o.tab, o.tab_src_first, o.ntab, o.s, o.first, o.swapped, o.w});
+    std::vector<int32_t> rd(P.reg_s.size()), rC(P.reg_s.size()), rs(P.reg_s.size());
+    for (size_t r = 0; r < P.reg_s.size(); r++) {
+      rd[r] = P.reg_depth[r];
+      rC[r] = (int32_t)slots_pair(k, P.reg_s[r]);
+      rs[r] = P.reg_s[r];
+    }
+    std::vector<TabDev> tv(p.blocks.size());
+    for (size_t b2 = 0; b2 < p.blocks.size(); b2++) tv[b2] = tabdev(tabs_[b2].p ? (int)b2 : -1);
+    L.d_ops.alloc(sizeof(LOp) * lops.size());
+    L.d_rd.alloc(4 * rd.size());
+    L.d_rC.alloc(4 * rC.size());
+    L.d_rs.alloc(4 * rs.size());
+    L.d_tv.alloc(sizeof(TabDev) * tv.size());
+    L.d_ctr.alloc(sizeof(uint64_t));
+    L.d_fail.alloc(4 * rest.size());
+    L.d_src.alloc(4 * rest.size());
+    L.d_fails.alloc(4 * rest.size());
+    HIP_CHECK(hipMemcpyAsync(L.d_ops.p, lops.data(), sizeof(LOp) * lops.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(L.d_rd.p, rd.data(), 4 * rd.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(L.d_rC.p, rC.data(), 4 * rC.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(L.d_rs.p, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(L.d_tv.p, tv.data(), sizeof(TabDev) * tv.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(L.d_src.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
+    L.grid = std::max(1, ncu) * 3;
+    LightArgs &la = L.la;
+    la.g = gd_;
+    la.lowcnt = g.lowcnt;
+    la.colr = d_col_.as<uint8_t>();
+    la.k = k;
+    la.src = L.d_src.as<int32_t>();
+    la.nsrc = (int)rest.size();
+    la.next = L.d_ctr.as<uint32_t>();
+    la.fail = L.d_fail.as<int32_t>();
+    la.nfail = L.d_ctr.as<uint32_t>() + 1;
+    la.ops = L.d_ops.as<LOp>();
+    la.nops = (int)lops.size();
+    la.reg_depth = L.d_rd.as<int32_t>();
+    la.reg_C = L.d_rC.as<int32_t>();
+    la.reg_s = L.d_rs.as<int32_t>();
+    la.nregs = (int)rd.size();
+    la.D = P.max_depth;
+    la.tabs = L.d_tv.as<TabDev>();
+    la.out = B.kind == BK_CYCLE ? tabs_[bi].as<uint64_t>() : nullptr;
+    la.s_out = B.size;
+    la.C_out = B.kind == BK_CYCLE ? table_C(p, (int)bi) : 0;
+    la.scratch_per_wg = light_scratch_;
+    la.lut = lut_device(g.device);
+    if (light_scratch_buf_.bytes < (size_t)light_scratch_ * L.grid)
+      light_scratch_buf_.alloc((size_t)light_scratch_ * L.grid);
+  }
+  for (auto &L : light_) L.la.scratch = light_scratch_buf_.as<uint8_t>();
+  (void)lut_device(g.device);  // built before any capture
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+Solver::~Solver() {
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+  if (own_st_) {
+    (void)hipStreamSynchronize(own_st_);
+    (void)hipStreamDestroy(own_st_);
+  }
+}
+
+void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof) {
+  const int k = p_.k;
+  hipStream_t st = st_;
+  const uint8_t *colr = d_col_.as<uint8_t>();
+  uint32_t *ovf = d_ovf_.as<uint32_t>();
+  // NodeJoin outputs keep their input's activity mask
+  std::vector<int> mown(P.reg_s.size());
+  for (size_t r = 0; r < mown.size(); r++) mown[r] = (int)r;
+  for (auto &op : P.ops)
+    if (op.kind == OP_NJ) mown[op.dst] = mown[op.a];
+  auto regdev = [&](int r) {
+    RegDev d;
+    d.val = regs_[r].val.as<uint64_t>();
+    d.mask = regs_[mown[r]].mask.as<uint64_t>();
+    d.C = (int)slots_pair(k, P.reg_s[r]);
+    d.s = P.reg_s[r];
+    return d;
+  };
+  auto lv = [&](int r) { return leveldev(P.reg_depth[r]); };
+  GroupDev grp;
+  grp.src = G.dsrc;
+  grp.B = (int)G.B;
+  grp.T = Tg;
+  grp.k = k;
+  grp.n_lim = G.hsrc[0];
+  for (int64_t i = 1; i < G.B; i++) grp.n_lim = std::max<int64_t>(grp.n_lim, G.hsrc[i]);
+  grp.dense = G.dense ? 1 : 0;
+  grp.prof = nullptr;
+  int max_low = 0;
+  for (int64_t i = 0; i < G.B; i++) max_low = std::max(max_low, g_.h_lowcnt[G.hsrc[i]]);
+  const int32_t *lowcnt_d = g_.lowcnt;
+  std::vector<char> built(P.max_depth + 2, 0);
+  std::function<void(int)> build = [&](int d) {  // sparse groups: entries of depth d
+    if (G.dense || built[d]) return;
+    if (prof) prof->begin("level_build_sparse", false, 0, 0, 0);
+    if (d == 1) {
+      launch_level_init(gd_, grp, lowcnt_d, max_low, leveldev(1), st);
+      launch_level_compact(grp, leveldev(1), st);
+    } else {
+      build(d - 1);
+      launch_level_next(gd_, grp, leveldev(d - 1), leveldev(d), st);
+    }
+    HIP_CHECK(hipGetLastError());
+    if (prof) prof->end();
+    built[d] = 1;
+  };
+  for (size_t oi = 0; oi < P.ops.size(); oi++) {
+    const Op &op = P.ops[oi];
+    static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
+                                  "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
+    if (op.kind == OP_INIT) build(1);
+    if (op.kind == OP_EJ) build(P.reg_depth[op.dst]);
+    grp.prof = nullptr;
+    if (prof) {
+      std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
+      if (op.kind == OP_EJ) {
+        // algorithmic bytes: a 4-byte neighbour id per scanned pair, an
+        // input row (plus the annotated edge's table row) per relaxation,
+        // an output row per entry
+        const double Cin = (double)slots_pair(k, P.reg_s[op.a]), Cout = (double)slots_pair(k, P.reg_s[op.dst]);
+        const double Ce = op.tab >= 0 ? (double)table_C(p_, op.tab) : 0.0;
+        grp.prof = prof->begin(nm.c_str(), true, 4.0, 8.0 * (Cin + Ce), 8.0 * Tg * Cout);
+      } else {
+        prof->begin(nm.c_str(), false, 0, 0, 0);
+      }
+    }
+    switch (op.kind) {
+      case OP_INIT: {
+        RegDev d = regdev(op.dst);
+        if (G.dense) {
+          launch_fill_u64(d.val, grp.n_lim * grp.B * (int64_t)Tg * d.C, st);
+          launch_fill_u64(d.mask, grp.n_lim, st);
+        }
+        launch_init(gd_, grp, lowcnt_d, max_low, colr, lv(op.dst), d, tabdev(op.tab), op.tab_src_first,
+                    tabdev(op.ntab), ovf, st);
+        break;
+      }
+      case OP_NJ:
+        launch_nj(gd_, grp, colr, lv(op.a), regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
+        break;
+      case OP_EJ:
+        launch_ej(gd_, grp, colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst), tabdev(op.tab),
+                  op.tab_src_first, ovf, st);
+        break;
+      case OP_AXPY:
+        launch_axpy(grp, lv(op.a), regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
+        break;
+      case OP_MROOT:
+        launch_mroot(grp, g_.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w, acc_, st);
+        break;
+      case OP_MU:
+      case OP_MV:
+        launch_munary(grp, g_.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w, op.kind == OP_MU, out,
+                      op.s, C_out, ovf, st);
+        break;
+      case OP_MEDGE:
+        launch_medge(gd_, grp, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), tabdev(op.tab),
+                     op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
+        break;
+      case OP_MEDGE_T:
+        launch_medge_t(gd_, grp, colr, lowcnt_d, max_low, tabdev(op.ntab), lv(op.b), regdev(op.b), tabdev(op.tab),
+                       op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
+        break;
+    }
+    HIP_CHECK(hipGetLastError());
+    if (prof) prof->end();
+  }
+  for (int d = 1; d <= P.max_depth; d++)
+    if (built[d]) launch_level_reset(grp, leveldev(d), st);
+}
+
+void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
+  const PBlock &B = p_.blocks[bi];
+  const int k = p_.k;
+  hipStream_t st = st_;
+  const uint8_t *colr = d_col_.as<uint8_t>();
+  uint32_t *ovf = d_ovf_.as<uint32_t>();
+  if (B.kind == BK_LEAF) {
+    int ec = B.edge_child[0];
+    if (prof) prof->begin("leaf", false, 0, 0, 0);
+    launch_leaf(gd_, Tg, k, colr, tabdev(B.node_child[0]), tabdev(ec), ec >= 0 ? B.edge_first_lo[0] : 0,
+                tabdev(B.node_child[1]), tabs_[bi].as<uint64_t>(), B.size, table_C(p_, (int)bi), ovf, st);
+    HIP_CHECK(hipGetLastError());
+    if (prof) prof->end();
+    return;
+  }
+  if (B.kind == BK_ROOT_SINGLE) {
+    launch_root_single(g_.n, Tg, tabdev(B.single_child), acc_, st);
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+  // cycle block
+  const Program &P = p_.programs[bi];
+  uint64_t *out = nullptr;
+  int C_out = 0;
+  if (B.kind == BK_CYCLE) {
+    out = tabs_[bi].as<uint64_t>();
+    C_out = table_C(p_, (int)bi);
+    int64_t keys = is_edge_table(p_, (int)bi) ? g_.m2 : g_.n;
+    launch_fill_u64(out, keys * Tg * C_out, st);
+  }
+  // 1. dense groups: the sources with the widest reach
+  for (int64_t i = 0; i < ndense_; i += z_.B_dense)
+    run_group(P, {d_src_.as<int32_t>() + i, sources_.data() + i, std::min<int64_t>(z_.B_dense, ndense_ - i), true}, Tg,
+              out, C_out, prof);
+  // 2. one workgroup per source for the rest
+  Light &L = light_[bi];
+  if (!L.src.empty()) {
+    L.la.T = Tg;
+    L.la.acc = acc_;
+    launch_fill_u64((uint64_t *)L.d_ctr.p, 1, st);
+    if (prof) prof->begin("light", false, 0, 0, 0);
+    launch_light(L.la, L.grid, st);
+    HIP_CHECK(hipGetLastError());
+    if (prof) prof->end();
+    if (probe && !L.probed) {
+      // learn what it hands back: from now on those sources run as groups
+      uint32_t hc[2];
+      HIP_CHECK(hipMemcpyAsync(hc, L.d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      std::vector<int32_t> f(hc[1]);
+      if (hc[1]) HIP_CHECK(hipMemcpy(f.data(), L.d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost));
+      std::sort(f.begin(), f.end(), std::greater<int32_t>());
+      std::vector<int32_t> keep;
+      {
+        std::vector<int32_t> fs = f;
+        std::sort(fs.begin(), fs.end());
+        for (int32_t s : L.src)
+          if (!std::binary_search(fs.begin(), fs.end(), s)) keep.push_back(s);
+      }
+      L.src = keep;
+      L.fails = f;
+      L.la.nsrc = (int)keep.size();
+      if (!keep.empty())
+        HIP_CHECK(hipMemcpyAsync(L.d_src.p, keep.data(), 4 * keep.size(), hipMemcpyHostToDevice, st));
+      if (!f.empty()) HIP_CHECK(hipMemcpyAsync(L.d_fails.p, f.data(), 4 * f.size(), hipMemcpyHostToDevice, st));
+      L.probed = true;
+    }
+  }
+  // 3. grouped path for what the one-workgroup tier does not take
+  if (!L.fails.empty()) {
+    for (int64_t i = 0; i < (int64_t)L.fails.size(); i += z_.B_sparse)
+      run_group(P,
+                {L.d_fails.as<int32_t>() + i, L.fails.data() + i,
+                 std::min<int64_t>(z_.B_sparse, (int64_t)L.fails.size() - i), fallback_dense_},
+                Tg, out, C_out, prof);
+  }
+}
+
+void Solver::enqueue(int Tg, bool seed_dev, bool probe, Profiler *prof) {
+  if (seed_dev) launch_colour_dev(g_.orig, g_.n, p_.k, d_param_.as<uint64_t>(), Tg, d_col_.as<uint8_t>(), st_);
+  launch_fill_u64(d_sum_.as<uint64_t>(), 2 * 64, st_);
+  launch_fill_u64((uint64_t *)d_ovf_.p, 32, st_);
+  if (acc_.per_src) launch_fill_u64(acc_.per_src, 2 * g_.n * (int64_t)Tg, st_);
+  for (size_t bi = 0; bi < p_.blocks.size(); bi++) enqueue_block(bi, Tg, probe, prof);
+}
+
+void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountResult &res,
+                                 std::vector<u128> *per_source) {
+  HIP_CHECK(hipSetDevice(g_.device));
+  hipStream_t st = st_;
+  if (per_source && !per_alloc_) {
+    d_per_.alloc(sizeof(uint64_t) * 2 * (size_t)g_.n * z_.T);
+    per_alloc_ = true;
+  }
+  acc_.per_src = per_source ? d_per_.as<uint64_t>() : nullptr;
+  bool probed = true;
+  std::vector<char> was_probed(light_.size());
+  for (size_t bi = 0; bi < light_.size(); bi++) {
+    was_probed[bi] = light_[bi].probed;
+    probed &= light_[bi].probed;
+  }
+  if (cs.from_seed) {
+    uint64_t prm[2] = {cs.seed, (uint64_t)t0};
+    HIP_CHECK(hipMemcpyAsync(d_param_.p, prm, sizeof(prm), hipMemcpyHostToDevice, st));
+  } else {
+    if (!d_hcol_.p) d_hcol_.alloc((size_t)g_.n * z_.T);
+    HIP_CHECK(hipMemcpyAsync(d_hcol_.p, cs.host + (size_t)t0 * g_.n, (size_t)g_.n * Tg, hipMemcpyHostToDevice, st));
+    launch_permute_colours(d_hcol_.as<uint8_t>(), g_.orig, g_.n, Tg, d_col_.as<uint8_t>(), st);
+  }
+  Profiler prof(st);
+  const bool graphs = opt_.use_graphs && probed && cs.from_seed && !per_source && !prof.on;
+  if (graphs) {
+    if (!exec_ || exec_T_ != Tg) {
+      if (exec_) (void)hipGraphExecDestroy(exec_);
+      if (graph_) (void)hipGraphDestroy(graph_);
+      exec_ = nullptr;
+      graph_ = nullptr;
+      HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue(Tg, true, false, nullptr);
+      } catch (...) {
+        hipGraph_t gtmp = nullptr;
+        (void)hipStreamEndCapture(st, &gtmp);
+        if (gtmp) (void)hipGraphDestroy(gtmp);
+        throw;
+      }
+      HIP_CHECK(hipStreamEndCapture(st, &graph_));
+      HIP_CHECK(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+      exec_T_ = Tg;
+    }
+    HIP_CHECK(hipGraphLaunch(exec_, st));
+    graph_replays++;
+  } else {
+    enqueue(Tg, cs.from_seed, true, prof.on ? &prof : nullptr);
+  }
+  // results of this trial group
+  std::vector<uint64_t> hs(2 * 64);
+  std::vector<uint32_t> ho(64);
+  HIP_CHECK(hipMemcpyAsync(hs.data(), d_sum_.p, sizeof(uint64_t) * 2 * 64, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(ho.data(), d_ovf_.p, sizeof(uint32_t) * 64, hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> lf(2 * light_.size(), 0);
+  for (size_t bi = 0; bi < light_.size(); bi++)
+    if (!light_[bi].src.empty()) HIP_CHECK(hipMemcpyAsync(&lf[2 * bi], light_[bi].d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+  std::vector<uint64_t> hp;
+  if (per_source) {
+    hp.resize(2 * (size_t)g_.n * Tg);
+    HIP_CHECK(hipMemcpyAsync(hp.data(), d_per_.p, sizeof(uint64_t) * hp.size(), hipMemcpyDeviceToHost, st));
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
+  prof.finish();
+  for (size_t bi = 0; bi < light_.size(); bi++)
+    if (was_probed[bi] && lf[2 * bi + 1] != 0)
+      fail(CC_E_DEVICE, "the one-workgroup tier handed back a source it completed before");
+  for (int t = 0; t < Tg; t++) {
+    res.exact[t0 + t] = (u128)hs[2 * t] | ((u128)hs[2 * t + 1] << 64);
+    res.overflow[t0 + t] = ho[t] ? 1 : 0;
+  }
+  if (per_source)
+    for (int64_t r = 0; r < g_.n; r++)
+      for (int t = 0; t < Tg; t++) {
+        size_t i = 2 * ((size_t)r * Tg + t);
+        (*per_source)[(size_t)(t0 + t) * g_.n + g_.h_orig[r]] = (u128)hp[i] | ((u128)hp[i + 1] << 64);
+      }
+}
+
+// ------------------------------------------------------------------ main
+CountResult run_count(const DevGraph &g, const Plan &p, int trials, const ColourSource &cs, const ExecOptions &opt,
+                      hipStream_t st, std::vector<u128> *per_source) {
+  if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
+  Solver S(g, p, trials, opt, st);
+  CountResult res;
+  res.exact.assign(trials, 0);
+  res.overflow.assign(trials, 0);
+  if (per_source) per_source->assign((size_t)trials * g.n, 0);
+  for (int t0 = 0; t0 < trials; t0 += S.T()) S.run_group_of_trials(t0, std::min(S.T(), trials - t0), cs, res, per_source);
+  return res;
+}
+
+// ------------------------------------------------------------------ batched
+//
+// All trials of one query through one Solver whose trial groups replay a
+// captured hipGraph.  Without a given tuning the trial-group size is tuned
+// online: candidates 1, 2, 4, ... each run one group to learn the one-
+// workgroup tier's hand-backs and one timed group as a graph replay (both on
+// real trials, whose results are kept), until the time per colouring stops
+// improving; the remaining trials run with the best.
+namespace {
+thread_local TuneReport g_last_tune;
+}
+
+TuneReport last_tune() { return g_last_tune; }
+
+CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t seed, const ExecOptions *given,
+                        hipStream_t st) {
+  if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
+  CountResult res;
+  res.exact.assign(trials, 0);
+  res.overflow.assign(trials, 0);
+  ColourSource cs;
+  cs.from_seed = true;
+  cs.seed = seed;
+  TuneReport rep;
+  int t0 = 0;
+  if (given) {
+    ExecOptions o = *given;
+    Solver S(g, p, trials, o, st);
+    for (; t0 < trials; t0 += S.T()) S.run_group_of_trials(t0, std::min(S.T(), trials - t0), cs, res, nullptr);
+    rep.trial_group = S.T();
+    rep.candidates = 0;
+    rep.replays = S.graph_replays;
+    g_last_tune = rep;
+    return res;
+  }
+  std::unique_ptr<Solver> best;
+  double best_per = 0;
+  int cand = 1;
+  while (t0 < trials) {
+    ExecOptions o;
+    o.use_graphs = 1;
+    o.trial_group = cand;
+    auto S = std::make_unique<Solver>(g, p, std::min(cand, trials), o, st);
+    const int T = S->T();
+    // group 1: learns the hand-backs (eager); group 2: a timed replay
+    S->run_group_of_trials(t0, std::min(T, trials - t0), cs, res, nullptr);
+    t0 += std::min(T, trials - t0);
+    if (t0 + T > trials) {  // not enough trials left to time this candidate
+      if (!best) best = std::move(S);
+      break;
+    }
+    auto a = std::chrono::steady_clock::now();
+    S->run_group_of_trials(t0, T, cs, res, nullptr);
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+    t0 += T;
+    rep.candidates++;
+    rep.tried_T[std::min(rep.candidates, 8) - 1] = T;
+    rep.tried_sec_per_colouring[std::min(rep.candidates, 8) - 1] = dt / T;
+    const bool better = !best || dt / T < best_per;
+    if (better) {
+      best_per = dt / T;
+      best = std::move(S);
+    }
+    if (!better || T < cand || T >= 64 || 2 * T > trials - t0) break;
+    cand = 2 * T;
+  }
+  if (best) {
+    for (; t0 < trials; t0 += best->T()) best->run_group_of_trials(t0, std::min(best->T(), trials - t0), cs, res, nullptr);
+    rep.trial_group = best->T();
+    rep.replays = best->graph_replays;
+  }
+  g_last_tune = rep;
   return res;
 }
 

@@ -81,6 +81,9 @@ inline int max_row_slots() { return 3584; }
 
 void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0, int T, uint8_t *out,
                    hipStream_t st);
+// param = {seed, first trial} in device memory
+void launch_colour_dev(const int32_t *orig, int64_t n, int k, const uint64_t *param, int T, uint8_t *out,
+                       hipStream_t st);
 void launch_permute_colours(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out,
                             hipStream_t st);
 void launch_fill_u8(uint8_t *p, int64_t n, hipStream_t st, uint8_t x = 0);

@@ -46,6 +46,17 @@ __global__ void k_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, i
   out[i] = (uint8_t)(((h >> 32) * (uint64_t)k) >> 32);
 }
 
+// the same, with (seed, first trial) read from device memory (replayable launches)
+__global__ void k_colour_dev(const int32_t *orig, int64_t n, int k, const uint64_t *param, int T, uint8_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * T) return;
+  int t = (int)(i / n);
+  int64_t r = i - (int64_t)t * n;
+  uint64_t key = mix64(param[0] + param[1] + (uint64_t)t);
+  uint64_t h = mix64(key ^ (uint64_t)(uint32_t)orig[r]);
+  out[i] = (uint8_t)(((h >> 32) * (uint64_t)k) >> 32);
+}
+
 __global__ void k_permute(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * T) return;
@@ -205,6 +216,12 @@ void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0,
                    hipStream_t st) {
   int64_t tot = n * T;
   hipLaunchKernelGGL(k_colour, dim3((unsigned)((tot + BLK - 1) / BLK)), dim3(BLK), 0, st, orig, n, k, seed, t0, T,
+                     out);
+}
+void launch_colour_dev(const int32_t *orig, int64_t n, int k, const uint64_t *param, int T, uint8_t *out,
+                       hipStream_t st) {
+  int64_t tot = n * T;
+  hipLaunchKernelGGL(k_colour_dev, dim3((unsigned)((tot + BLK - 1) / BLK)), dim3(BLK), 0, st, orig, n, k, param, T,
                      out);
 }
 void launch_permute_colours(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out,
