@@ -30,15 +30,83 @@ namespace cc {
 
 namespace {
 
+// Device memory of the solves is recycled: a released block goes to a
+// per-device cache and is handed out again for a request of similar size, so
+// solves do not pay hipMalloc / hipFree (whose implicit device-wide
+// synchronisation would also serialise solves running side by side).  Blocks
+// are released only after the owning solve has synchronised its stream.
+struct BlockCache {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void *>> free;  // device -> size -> block
+  std::map<int, size_t> cached;
+};
+BlockCache &block_cache() {
+  static BlockCache *c = new BlockCache;  // outlives every solve
+  return *c;
+}
+size_t round_block(size_t b) {
+  if (b < ((size_t)1 << 20)) return (b + 255) & ~(size_t)255;
+  size_t q = ((size_t)1 << (63 - __builtin_clzll(b))) / 8;  // 8 size classes per power of two
+  return (b + q - 1) / q * q;
+}
+int cur_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+void *cache_take(int dev, size_t b, size_t &got) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto &fl = c.free[dev];
+  auto it = fl.lower_bound(b);
+  if (it == fl.end() || it->first > b + b / 4) return nullptr;
+  void *p = it->second;
+  got = it->first;
+  c.cached[dev] -= got;
+  fl.erase(it);
+  return p;
+}
+void cache_give(int dev, void *p, size_t b) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.free[dev].insert({b, p});
+  c.cached[dev] += b;
+}
+void cache_trim(int dev) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto &kv : c.free[dev]) (void)hipFree(kv.second);
+  c.free[dev].clear();
+  c.cached[dev] = 0;
+}
+size_t cache_bytes(int dev) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  return c.cached[dev];
+}
+
 struct DevMem {
   void *p = nullptr;
   size_t bytes = 0;
+  int dev = 0;
   DevMem() = default;
   explicit DevMem(size_t b) { alloc(b); }
   void alloc(size_t b) {
     release();
     if (b == 0) b = 8;
+    b = round_block(b);
+    dev = cur_device();
+    size_t got = 0;
+    if ((p = cache_take(dev, b, got))) {
+      bytes = got;
+      return;
+    }
     hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {  // give the cached blocks back to the device and retry once
+      (void)hipGetLastError();
+      cache_trim(dev);
+      e = hipMalloc(&p, b);
+    }
     if (e != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
@@ -47,14 +115,14 @@ struct DevMem {
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) cache_give(dev, p, bytes);
     p = nullptr;
     bytes = 0;
   }
   ~DevMem() { release(); }
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
-  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes) {
+  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) {
     o.p = nullptr;
     o.bytes = 0;
   }
@@ -63,6 +131,7 @@ struct DevMem {
       release();
       p = o.p;
       bytes = o.bytes;
+      dev = o.dev;
       o.p = nullptr;
       o.bytes = 0;
     }
@@ -96,18 +165,6 @@ struct Sizing {
   int64_t dense_cut; // number of leading sources run dense
 };
 
-uint64_t program_bytes_per_vb(const Plan &p, int T) {
-  // bytes per (vertex, source) pair over all registers of all programs (max)
-  uint64_t best = 0;
-  for (size_t i = 0; i < p.blocks.size(); i++) {
-    const Program &P = p.programs[i];
-    uint64_t b = 0;
-    for (int s : P.reg_s) b += (uint64_t)slots_pair(p.k, s) * T * 8 + 1 + 8;
-    best = std::max(best, b);
-  }
-  return best;
-}
-
 uint64_t table_bytes(const DevGraph &g, const Plan &p, int T) {
   uint64_t b = 0;
   for (size_t i = 0; i < p.blocks.size(); i++) {
@@ -119,41 +176,71 @@ uint64_t table_bytes(const DevGraph &g, const Plan &p, int T) {
   return b;
 }
 
-uint64_t free_bytes() {
+uint64_t free_bytes() {  // free on the device, counting the recycled blocks as free
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
-  return (uint64_t)fr;
+  return (uint64_t)fr + cache_bytes(cur_device());
+}
+
+// scratch of the one-workgroup tier per workgroup: enough for the frontiers a
+// graph of this size can have, within 2 MiB (larger frontiers are handed back)
+int64_t light_scratch_bytes(const DevGraph &g, int T) {
+  int64_t b = (int64_t)g.n * T * 128;
+  if (const char *ev = getenv("CC_LIGHT_SCRATCH")) return std::max<int64_t>(4096, atoll(ev));
+  return std::max<int64_t>(64 << 10, std::min<int64_t>(b, 2 << 20));
+}
+int light_grid(int device) {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) ncu = 256;
+  return std::max(1, ncu) * 3;
+}
+
+// Device bytes of a solve with trial groups of T: a part that does not
+// depend on the sources per group B and a part per source of B.
+struct Bytes {
+  uint64_t fixed, per_B;
+};
+Bytes solver_bytes(const DevGraph &g, const Plan &p, int T) {
+  const uint64_t n = (uint64_t)std::max<int64_t>(1, g.n);
+  uint64_t slots = 0, nregs = 0;
+  int dmax = 1;
+  for (auto &P : p.programs) {
+    uint64_t sl = 0;
+    for (int s : P.reg_s) sl += slots_pair(p.k, s);
+    slots = std::max(slots, sl);
+    nregs = std::max<uint64_t>(nregs, P.reg_s.size());
+    dmax = std::max(dmax, P.max_depth);
+  }
+  Bytes b;
+  b.fixed = table_bytes(g, p, T) + 2 * n * T                   // tables, colours (+ host-colour staging)
+            + nregs * 8 * n                                    // activity masks
+            + (uint64_t)dmax * (12 * n + 4 * (n / 4096 + 2))   // level marks and bases
+            + (uint64_t)light_scratch_bytes(g, T) * light_grid(g.device) + (64 << 20);
+  b.per_B = 8 * n * T * slots + (uint64_t)dmax * 8 * n;        // registers, level lists
+  return b;
 }
 
 Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt, uint64_t budget) {
   Sizing z{};
   z.T = opt.trial_group > 0 ? std::min(opt.trial_group, 64) : std::min(trials, 64);
   if (z.T < 1) z.T = 1;
+  // one workgroup covers every (source, trial, slot) of a vertex
+  int cmax = 1;
+  for (auto &P : p.programs)
+    for (int s : P.reg_s) cmax = std::max(cmax, (int)slots_pair(p.k, s));
+  for (auto &B2 : p.blocks)
+    if (B2.kind == BK_CYCLE) cmax = std::max(cmax, (int)binom(p.k - 1, B2.size - 1));
+  if (cmax > max_row_slots()) fail(CC_E_UNSUPPORTED, "signature tables too wide for one workgroup");
+  while ((int64_t)z.T * cmax > max_row_slots()) z.T = std::max(1, z.T / 2);
   for (;;) {
-    uint64_t tabs = table_bytes(g, p, z.T);
-    uint64_t per_vb = program_bytes_per_vb(p, z.T);
-    uint64_t n = (uint64_t)std::max<int64_t>(1, g.n);
-    uint64_t left = budget > tabs ? budget - tabs : 0;
-    int64_t B = per_vb ? (int64_t)(left / (per_vb * n)) : 64;
+    Bytes b = solver_bytes(g, p, z.T);
+    int64_t B = budget > b.fixed && b.per_B ? (int64_t)((budget - b.fixed) / b.per_B) : 0;
     if (B >= 1 || z.T == 1) {
-      B = std::max<int64_t>(1, std::min<int64_t>(B, 64));
+      if (B < 1) fail(CC_E_NOMEM, "plan does not fit the device memory budget");
+      B = std::min<int64_t>(B, 64);
       if (opt.group_sources > 0) B = std::min<int64_t>(B, opt.group_sources);
-      // one workgroup covers every (source, trial, slot) of a vertex
-      int cmax = 1;
-      for (auto &P : p.programs)
-        for (int s : P.reg_s) cmax = std::max(cmax, (int)slots_pair(p.k, s));
-      for (auto &B2 : p.blocks)
-        if (B2.kind == BK_CYCLE) cmax = std::max(cmax, (int)binom(p.k - 1, B2.size - 1));
-      if ((int64_t)z.T * cmax > max_row_slots()) {
-        if (z.T > 1) {
-          z.T = std::max(1, z.T / 2);
-          continue;
-        }
-        fail(CC_E_UNSUPPORTED, "signature tables too wide for one workgroup");
-      }
       z.B_dense = (int)B;
       z.B_sparse = (int)B;
-      if (tabs + per_vb * n * B > budget) fail(CC_E_NOMEM, "plan does not fit the device memory budget");
       return z;
     }
     z.T = std::max(1, z.T / 2);
@@ -293,10 +380,9 @@ void dump_programs(const Plan &p) {
 uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt) {
   int T = std::min(std::max(trials, 1), 64);
   if (opt.trial_group > 0) T = std::min(T, opt.trial_group);
-  uint64_t tabs = table_bytes(g, p, T);
-  uint64_t per_vb = program_bytes_per_vb(p, T);
   int B = opt.group_sources > 0 ? std::min(opt.group_sources, 64) : 64;
-  return tabs + per_vb * (uint64_t)g.n * B + (uint64_t)g.n * T;
+  Bytes b = solver_bytes(g, p, T);
+  return b.fixed + b.per_B * (uint64_t)B;
 }
 
 void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t st) {
@@ -450,7 +536,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   }
   if (const char *ev = getenv("CC_LIGHT"))
     if (!strcmp(ev, "0")) use_light_ = false;
-  if (const char *ev = getenv("CC_LIGHT_SCRATCH")) light_scratch_ = std::max<int64_t>(4096, atoll(ev));
+  light_scratch_ = light_scratch_bytes(g, T);
   if (const char *ev = getenv("CC_FALLBACK"))
     if (!strcmp(ev, "dense")) fallback_dense_ = true;
   const int Bmax = std::max(z_.B_dense, z_.B_sparse);
@@ -502,8 +588,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   }
   // one-workgroup tier per cycle block
   light_.resize(p.blocks.size());
-  int ncu = 0;
-  HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g.device));
+  const int lgrid = light_grid(g.device);
   std::vector<int32_t> rest(sources_.begin() + ndense_, sources_.end());
   for (size_t bi = 0; bi < p.blocks.size(); bi++) {
     const PBlock &B = p.blocks[bi];
@@ -551,7 +636,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
     HIP_CHECK(hipMemcpyAsync(L.d_rs.p, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st));
     HIP_CHECK(hipMemcpyAsync(L.d_tv.p, tv.data(), sizeof(TabDev) * tv.size(), hipMemcpyHostToDevice, st));
     HIP_CHECK(hipMemcpyAsync(L.d_src.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
-    L.grid = std::max(1, ncu) * 3;
+    L.grid = lgrid;
     LightArgs &la = L.la;
     la.g = gd_;
     la.lowcnt = g.lowcnt;
