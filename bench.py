@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--batch-trials", type=int, default=6,
                     help="colourings solved in one batched call (0: skip the batched measurement)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first run one 1 GiB device-to-device copy, so that hardware byte counters "
+                    help="first run four copies of 1 GiB on the device, so that hardware byte counters "
                          "collected over this run can be scaled against a kernel of known traffic")
     return ap.parse_args()
 
@@ -114,26 +114,55 @@ def roofline(stats):
 
 
 def cpu_baseline(g, k, E, seed, budget_s):
-    """Oracle (as it stands) on a systematic sample of root sources: every
-    K-th source in degree order, K doubled until one pass fits the budget.
-    The sample's time is scaled by K to the whole solve."""
+    """The oracle (as it stands) on a bounded, stratified sample of root
+    sources, scaled to the whole solve by a ratio estimator.
+
+    The cost of a root source is concentrated in the hubs, so sources are
+    stratified by a work proxy -- W(u), the summed degree of u's lower
+    neighbours -- in powers of two.  From the lightest stratum up, each
+    stratum's sample (at most 64 sources, systematic) is run as one oracle call
+    (its OpenMP threads take the sources in parallel) and its CPU seconds are
+    scaled by the stratum's total proxy over the sample's.  Strata beyond the
+    time budget are not run: they are priced at the CPU seconds per proxy unit
+    of the heaviest stratum that ran.  Wall time on C cores = CPU seconds / C."""
     from oracle import oracle as O
     chi = O.colours(g.n, k, seed, 0)
-    deg = g.degrees()
-    order = np.lexsort((np.arange(g.n), deg))[::-1]  # highest degree first
-    K = 4096
-    while True:
-        sample = order[K // 2::K]
-        t0 = time.perf_counter()
-        O.db(g, k, E, chi, reverse_ties=False, sources=sample)
-        dt = time.perf_counter() - t0
-        if dt > budget_s / 4 or K <= 64:
-            break
-        K //= 2
-    est_full = dt * K
-    return dict(value=g.m / est_full, unit="colourings*edges/s", cores=O.threads(), kind="oracle",
-                sample=f"DB oracle, root sources every {K}th in degree order ({len(sample)} of {g.n}), "
-                       f"non-root tables in full; {dt:.2f} s scaled x{K}")
+    deg = g.degrees().astype(np.int64)
+    order = np.lexsort((np.arange(g.n), deg))  # ascending (degree, id): the library's order
+    rank = np.empty(g.n, dtype=np.int64)
+    rank[order] = np.arange(g.n)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    dst = g.col.astype(np.int64)
+    low = rank[dst] < rank[src]
+    W = np.bincount(src[low], weights=deg[dst[low]], minlength=g.n)
+    cand = np.nonzero(W > 0)[0]
+    strata = np.floor(np.log2(W[cand])).astype(np.int64)
+    cpu_total, spent, used, ran, skipped = 0.0, 0.0, [], 0, 0
+    last_rate = None
+    cores = O.threads()
+    for s_id in np.unique(strata):
+        members = cand[strata == s_id]
+        members = members[np.argsort(W[members])]
+        step = max(1, len(members) // 64)
+        sample = members[step // 2::step][:64]
+        if spent < budget_s:
+            c0, t0 = time.process_time(), time.perf_counter()
+            O.db(g, k, E, chi, reverse_ties=False, sources=sample)
+            cpu = time.process_time() - c0
+            spent += time.perf_counter() - t0
+            last_rate = cpu / W[sample].sum()
+            cpu_total += cpu * W[members].sum() / W[sample].sum()
+            used.append(f"2^{s_id}:{len(sample)}/{len(members)}")
+            ran += len(sample)
+        else:
+            cpu_total += last_rate * W[members].sum()
+            skipped += len(members)
+    wall = cpu_total / cores
+    return dict(value=g.m / wall, unit="colourings*edges/s", cores=cores, kind="oracle",
+                sample=(f"DB oracle on {ran} root sources stratified by lower-neighbour degree sum "
+                        f"(strata sampled/size: {' '.join(used)}); {skipped} sources in heavier strata priced "
+                        f"at the heaviest sampled stratum's CPU s per unit; {spent:.1f} s measured; "
+                        f"estimated {cpu_total:.0f} CPU s for the whole solve, / {cores} cores"))
 
 
 def main():
@@ -151,12 +180,7 @@ def main():
     dg = cc.Graph.from_csr(g)
     q = cc.Query(k, E)
     if a.copy_probe:
-        import torch
-        x = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
+        cc.probe_copy(1 << 30, 4)  # 4 copies of 1 GiB: 8 GiB read + written
     for i in range(a.warmup):
         cc.count(dg, q, seed0 + 1000 + i, trials)
     times, results = [], []
@@ -197,6 +221,8 @@ def main():
     }
     if prof:
         out["roofline"], out["kernels"] = roofline(stats)
+        # the rate of a plain streaming copy on this device: what an HBM-bound kernel can reach
+        out["roofline"]["copy_probe_GBps"] = cc.probe_copy(1 << 30, 10)
     if a.batch_trials > 0:
         # batched form: one call, trial groups replaying a captured hipGraph,
         # the trial-group size tuned online on the call's first colourings

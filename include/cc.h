@@ -244,6 +244,15 @@ typedef struct {
 } cc_kernel_stat;
 
 cc_status cc_profile_enable(int32_t on);
+
+/*
+ * A plain streaming copy between two device buffers of `bytes` (a multiple
+ * of 16) that the library allocates, repeated `reps` times on a stream of its
+ * own; *gbps = 2 * bytes * reps / elapsed (bytes read + written per second).
+ * A kernel of known traffic: it calibrates hardware byte counters, and its
+ * rate is the bandwidth a streaming kernel reaches on this device.
+ */
+cc_status cc_probe_copy(uint64_t bytes, int32_t reps, double *gbps);
 /* Copy up to `cap` entries into `out` (host), set *len to the number of
  * kernels recorded, and reset the statistics. */
 cc_status cc_profile_read(cc_kernel_stat *out, int32_t cap, int32_t *len);

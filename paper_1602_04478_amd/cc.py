@@ -21,7 +21,7 @@ STATUS = {0: "CC_OK", 1: "CC_E_ARG", 2: "CC_E_GRAPH", 3: "CC_E_QUERY_TW", 4: "CC
 EXPORTS = ["cc_graph_create", "cc_graph_destroy", "cc_graph_info", "cc_query_create", "cc_query_destroy",
            "cc_query_info", "cc_query_plan", "cc_footprint", "cc_colors", "cc_count", "cc_count_colors",
            "cc_count_batch", "cc_server_create", "cc_server_add_graph", "cc_server_submit", "cc_server_poll",
-           "cc_server_drain", "cc_server_destroy", "cc_last_tune_report", "cc_profile_enable", "cc_profile_read",
+           "cc_server_drain", "cc_server_destroy", "cc_last_tune_report", "cc_profile_enable", "cc_profile_read", "cc_probe_copy",
            "cc_status_str", "cc_last_error"]
 
 
@@ -297,6 +297,13 @@ class Server:
         if self.h:
             _check(lib().cc_server_destroy(self.h))
             self.h = None
+
+
+def probe_copy(nbytes: int, reps: int = 10) -> float:
+    """GB/s (read + write) of a plain device copy of nbytes (cc_probe_copy)."""
+    r = ctypes.c_double()
+    _check(lib().cc_probe_copy(nbytes, reps, ctypes.byref(r)))
+    return r.value
 
 
 def profile_enable(on: bool = True):

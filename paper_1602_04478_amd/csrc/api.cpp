@@ -241,6 +241,13 @@ cc_status cc_last_tune_report(cc_tune_report *out) {
   });
 }
 
+cc_status cc_probe_copy(uint64_t bytes, int32_t reps, double *gbps) {
+  return guard([&] {
+    if (!gbps || reps < 1 || bytes < 16 || bytes % 16) cc::fail(CC_E_ARG, "bad argument");
+    *gbps = cc::probe_copy(bytes, reps);
+  });
+}
+
 cc_status cc_profile_enable(int32_t on) {
   return guard([&] { cc::profile_enable(on != 0); });
 }

@@ -173,6 +173,7 @@ struct KernelProfile {
 };
 std::vector<KernelProfile> profile_read();
 void dump_programs(const Plan &p);  // the cycle programs, to stderr
+double probe_copy(uint64_t bytes, int reps);  // GB/s of a plain device copy (read + write)
 
 double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf);
 

@@ -290,12 +290,13 @@ struct Profiler {
   };
   std::vector<Rec> recs;
   std::vector<uint64_t *> ctrs;
+  static constexpr int kMaxCtr = 16384;
   int nctr = 0;
   DevMem ctrmem;
   explicit Profiler(hipStream_t s) : st(s) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     on = g_prof_on;
-    if (on) ctrmem.alloc(sizeof(uint64_t) * 3 * 65536);
+    if (on) ctrmem.alloc(sizeof(uint64_t) * 3 * PROF_LANES * kMaxCtr);
   }
   // returns a zeroed counter triple for an EdgeJoin launch (or null)
   uint64_t *begin(const char *name, bool counters, double per_scan, double per_active, double per_entry) {
@@ -304,10 +305,10 @@ struct Profiler {
     r.name = name;
     r.ctr = -1;
     uint64_t *c = nullptr;
-    if (counters && nctr < 65536) {
+    if (counters && nctr < kMaxCtr) {
       r.ctr = nctr++;
-      c = ctrmem.as<uint64_t>() + 3 * r.ctr;
-      launch_fill_u64(c, 3, st);
+      c = ctrmem.as<uint64_t>() + (size_t)3 * PROF_LANES * r.ctr;
+      launch_fill_u64(c, 3 * PROF_LANES, st);
     }
     r.a = take_event();
     r.b = take_event();
@@ -325,8 +326,12 @@ struct Profiler {
   void finish() {
     if (!on) return;
     HIP_CHECK(hipStreamSynchronize(st));
-    std::vector<uint64_t> h(3 * (size_t)std::max(1, nctr));
-    if (nctr) HIP_CHECK(hipMemcpy(h.data(), ctrmem.p, sizeof(uint64_t) * 3 * nctr, hipMemcpyDeviceToHost));
+    std::vector<uint64_t> hl((size_t)3 * PROF_LANES * std::max(1, nctr)), h(3 * (size_t)std::max(1, nctr), 0);
+    if (nctr)
+      HIP_CHECK(hipMemcpy(hl.data(), ctrmem.p, sizeof(uint64_t) * 3 * PROF_LANES * nctr, hipMemcpyDeviceToHost));
+    for (int r = 0; r < nctr; r++)
+      for (int l = 0; l < PROF_LANES; l++)
+        for (int i = 0; i < 3; i++) h[3 * r + i] += hl[((size_t)r * PROF_LANES + l) * 3 + i];
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &r : recs) {
       float ms = 0;
@@ -361,6 +366,25 @@ std::vector<KernelProfile> profile_read() {
   }
   g_prof.clear();
   return v;
+}
+
+double probe_copy(uint64_t bytes, int reps) {
+  DevMem a(bytes), b(bytes);
+  hipStream_t st;
+  HIP_CHECK(hipStreamCreate(&st));
+  launch_fill_u64(a.as<uint64_t>(), (int64_t)(bytes / 8), st);
+  launch_copy16(a.p, b.p, (int64_t)(bytes / 16), st);  // warm
+  hipEvent_t e0 = take_event(), e1 = take_event();
+  HIP_CHECK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; i++) launch_copy16(a.p, b.p, (int64_t)(bytes / 16), st);
+  HIP_CHECK(hipEventRecord(e1, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  float ms = 0;
+  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  give_event(e0);
+  give_event(e1);
+  (void)hipStreamDestroy(st);
+  return 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
 }
 
 void dump_programs(const Plan &p) {

@@ -393,9 +393,10 @@ __global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uin
       n_ent += __shfl_xor(n_ent, o);
     }
     if (lane == 0) {
-      atomicAdd((unsigned long long *)&grp.prof[0], (unsigned long long)n_scan);
-      atomicAdd((unsigned long long *)&grp.prof[1], (unsigned long long)n_rows);
-      atomicAdd((unsigned long long *)&grp.prof[2], (unsigned long long)n_ent);
+      uint64_t *pc = grp.prof + 3 * (blockIdx.x % PROF_LANES);  // spread over lanes: no hot address
+      atomicAdd((unsigned long long *)&pc[0], (unsigned long long)n_scan);
+      atomicAdd((unsigned long long *)&pc[1], (unsigned long long)n_rows);
+      atomicAdd((unsigned long long *)&pc[2], (unsigned long long)n_ent);
     }
   }
 }
@@ -567,9 +568,10 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
       n_ent += __shfl_xor(n_ent, o);
     }
     if (lane == 0) {
-      atomicAdd((unsigned long long *)&grp.prof[0], (unsigned long long)n_scan);
-      atomicAdd((unsigned long long *)&grp.prof[1], (unsigned long long)n_rows);
-      atomicAdd((unsigned long long *)&grp.prof[2], (unsigned long long)n_ent);
+      uint64_t *pc = grp.prof + 3 * (blockIdx.x % PROF_LANES);  // spread over lanes: no hot address
+      atomicAdd((unsigned long long *)&pc[0], (unsigned long long)n_scan);
+      atomicAdd((unsigned long long *)&pc[1], (unsigned long long)n_rows);
+      atomicAdd((unsigned long long *)&pc[2], (unsigned long long)n_ent);
     }
   }
 }

@@ -42,6 +42,9 @@ struct RegDev {
 };
 
 // The group being processed.
+// EdgeJoin work counters (profiling): PROF_LANES triples summed by the host
+constexpr int PROF_LANES = 64;
+
 struct GroupDev {
   const int32_t *src;  // source ranks, [B]
   int B;
@@ -84,6 +87,7 @@ void launch_colour(const int32_t *orig, int64_t n, int k, uint64_t seed, int t0,
 // param = {seed, first trial} in device memory
 void launch_colour_dev(const int32_t *orig, int64_t n, int k, const uint64_t *param, int T, uint8_t *out,
                        hipStream_t st);
+void launch_copy16(const void *a, void *b, int64_t n16, hipStream_t st);  // n16 16-byte words
 void launch_permute_colours(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out,
                             hipStream_t st);
 void launch_fill_u8(uint8_t *p, int64_t n, hipStream_t st, uint8_t x = 0);

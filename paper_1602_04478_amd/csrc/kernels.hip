@@ -57,6 +57,12 @@ __global__ void k_colour_dev(const int32_t *orig, int64_t n, int k, const uint64
   out[i] = (uint8_t)(((h >> 32) * (uint64_t)k) >> 32);
 }
 
+// plain streaming copy, 16 bytes per lane per step
+__global__ void k_copy16(const uint4 *__restrict__ a, uint4 *__restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
 __global__ void k_permute(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * T) return;
@@ -223,6 +229,10 @@ void launch_colour_dev(const int32_t *orig, int64_t n, int k, const uint64_t *pa
   int64_t tot = n * T;
   hipLaunchKernelGGL(k_colour_dev, dim3((unsigned)((tot + BLK - 1) / BLK)), dim3(BLK), 0, st, orig, n, k, param, T,
                      out);
+}
+void launch_copy16(const void *a, void *b, int64_t n16, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)std::min<int64_t>((n16 + BLK - 1) / BLK, 1 << 16)), dim3(BLK), 0, st,
+                     (const uint4 *)a, (uint4 *)b, n16);
 }
 void launch_permute_colours(const uint8_t *by_orig, const int32_t *orig, int64_t n, int T, uint8_t *out,
                             hipStream_t st) {
