@@ -13,7 +13,7 @@ Generators
 ----------
 * ``erdos_renyi(n, avg_degree, seed)``  G(n, p) with p = avg_degree/(n-1).
 * ``chung_lu(n, mean, gamma, w_max, seed)``  the random power-law model of
-  the paper's analysis (Section 8: edge (i, j) present independently with
+  the paper's analysis (Appendix A: edge (i, j) present independently with
   probability min(1, w_i w_j / sum(w))), sampled in O(n + m) by skipping
   over non-edges with geometric jumps (the Miller-Hagberg scheme).
 * ``complete(n)``, ``from_edges(n, edges)`` and small helpers for tests.

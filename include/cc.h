@@ -11,11 +11,11 @@
  * mean colourful count is an unbiased estimate of n(G,Q); dividing by aut(Q)
  * turns matches into copies).
  *
- * The counts come from the degree-based dynamic program of Section 4: the
+ * The counts come from the degree-based dynamic program of Section 5: the
  * query is decomposed into leaf-edge and cycle blocks (Section 4.1), and each
  * cycle is solved by partitioning its colourful matches by the highest
  * matched vertex in the degree order (Eq. (1)) and joining high-starting
- * path tables (NodeJoin / EdgeJoin, Section 4.4).  All arithmetic is exact
+ * path tables (NodeJoin / EdgeJoin, Section 5.2).  All arithmetic is exact
  * unsigned integer arithmetic; overflow is detected, never wrapped.
  *
  * Conventions for every call:
@@ -84,7 +84,7 @@ typedef struct {
  *   row_ptr  host, int64[n+1], row_ptr[0] = 0, non-decreasing.
  *   col      host, int32[row_ptr[n]]: neighbours of v are col[row_ptr[v] .. row_ptr[v+1]).
  *            Every undirected edge {u,v} appears as v in u's row and u in v's row.
- * The library orders vertices by (degree, id) ascending (Section 4.3, degree
+ * The library orders vertices by (degree, id) ascending (Section 5.1, degree
  * ordering), relabels them by that rank and sorts every neighbour list, so the
  * lower neighbours of a vertex form a prefix of its list.
  * Errors: CC_E_ARG, CC_E_GRAPH (see CC_GRAPH_CLEAN), CC_E_NOMEM, CC_E_DEVICE.
@@ -101,7 +101,7 @@ cc_status cc_graph_info(cc_graph g, int64_t *n, int64_t *m, int64_t *max_degree)
  * Plan a query: k nodes 0..k-1, num_edges undirected edges given as pairs in
  * `edges` (host, int32[2*num_edges]).  The query must be simple and connected
  * with 2 <= k <= 12.  The planner enumerates decomposition trees (Section 4.1,
- * Cases 1-3) and picks one by the heuristic of Section 5 (shortest longest
+ * Cases 1-3) and picks one by the heuristic of Section 6 (shortest longest
  * cycle, then fewest boundary nodes, then fewest annotations), among the trees
  * whose two-boundary blocks have adjacent boundary nodes.
  * Errors: CC_E_ARG, CC_E_K_RANGE, CC_E_QUERY_DISCONNECTED, CC_E_QUERY_TW, CC_E_UNSUPPORTED.

@@ -10,7 +10,7 @@
 //          Preliminaries: injective, edge-preserving maps; colourful = all k
 //          colours used).
 //   o3_*   the degree-based (DB) dynamic program over the decomposition tree
-//          (Sections 4.1-4.4), written from the paper's description:
+//          (Sections 4.1-5.2), written from the paper's description:
 //            - decomposition by contracting leaf edges and contractible
 //              cycles (Cases 1-3 of Section 4.1);
 //            - cycles solved by partitioning the colourful matches by their
@@ -19,7 +19,7 @@
 //              NodeJoin/EdgeJoin (Fig. "DB Procedure for General Cycle
 //              Blocks"), boundary images recorded in extra fields when a
 //              boundary node lies strictly inside a path (configurations
-//              (A)/(B), Section 4.3), and merged with a1 n a2 = {chi(u),chi(v)};
+//              (A)/(B), Section 5.1), and merged with a1 n a2 = {chi(u),chi(v)};
 //            - leaf blocks by joining the annotations of a, (a,b) and b;
 //            - the root by counting (cycle) or summing the table (singleton).
 //   Colouring contract: chi_t(v) = ((mix(mix(seed + t) ^ v) >> 32) * k) >> 32

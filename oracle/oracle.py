@@ -18,7 +18,7 @@ colouring chi with k colours):
                         elimination being a sum over one data vertex of a
                         product of vector/matrix factors.
 * ``db``             -- the paper's degree-based dynamic program (Sections
-                        4.1-4.4), in C, with 128-bit counts.
+                        4.1-5.2), in C, with 128-bit counts.
 
 ``colours`` implements the colouring contract: for trial t,
 chi_t(v) = ((mix(mix(seed + t) XOR v) >> 32) * k) >> 32, mix = splitmix64's

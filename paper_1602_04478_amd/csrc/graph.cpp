@@ -1,4 +1,4 @@
-// Graph residency: validate the CSR, order vertices by degree (Section 4.3,
+// Graph residency: validate the CSR, order vertices by degree (Section 5.1,
 // degree ordering: ascending degree, ties by id), relabel every vertex by its
 // rank and sort each neighbour list by rank, so that the neighbours lower than
 // any given vertex form a prefix of its list.  Also builds the reverse-slot

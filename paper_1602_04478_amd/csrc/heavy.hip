@@ -11,13 +11,16 @@
 // deterministic compaction numbers the marks in (vertex, source) order, so the
 // entry of (v, b) is base[v] + popcount of the marks of v below b.
 //
-// EdgeJoin is a pull: a team of lanes owns one output entry (w, b) and strides
-// over w's neighbours below u_b; each lane reads the whole row of its
-// neighbour's entry and adds every input slot to the output slot it becomes
-// (data edge: the signature gains chi(v) -- Section 4.3, Procedure 1) or to the
-// output slots of all its products with the edge table (annotated edge:
-// EdgeJoin of Section 4.4), accumulating in LDS.  NodeJoin, AXPY and the
-// merges are flat: one thread per output slot.
+// EdgeJoin is a pull.  The main kernel is vertex-major: one wavefront owns an
+// output vertex w and all sources of the group at once (lane = (source,
+// trial)), reads w's neighbour list once with each neighbour's per-vertex
+// source bits, and every lane adds the input row (v, b) of its own source into
+// its own LDS column, slot by slot to the output slot it becomes (data edge:
+// the signature gains chi(v) -- Section 5.1, DB Procedure 1) or to every
+// output slot through the products with the edge table (annotated edge:
+// EdgeJoin of Section 5.2).  Rows wider than an LDS column per lane allows
+// take an entry-major kernel (a wavefront per output entry).  NodeJoin, AXPY
+// and the merges are flat: one thread per output slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -233,8 +236,8 @@ constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps
 //           pairs i, i + 64, ..., loading four input values before it adds
 //           them, so rows are read contiguously and many loads are in flight.
 // Data edge: input slot c goes to the output slot with chi(v) added (Section
-// 4.3).  Annotated edge: lanes take (neighbour, output slot) pairs and sum the
-// products over the splits of the output signature (EdgeJoin of Section 4.4).
+// 5.1).  Annotated edge: lanes take (neighbour, output slot) pairs and sum the
+// products over the splits of the output signature (EdgeJoin of Section 5.2).
 // Accumulation in LDS in split 32-bit halves (non-returning adds that cannot
 // overflow), joined and checked when the row is written.
 template <bool ANN>

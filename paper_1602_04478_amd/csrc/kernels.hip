@@ -12,7 +12,7 @@
 // colour subset) of one output key and sums, over the joined entries, the
 // products over all ways to split its subset between the operands (the
 // disjoint-signature condition of NodeJoin / EdgeJoin / the cycle merge,
-// Section 4.4).  Sums and products are checked: a table entry that leaves 64
+// Sections 5.1-5.2).  Sums and products are checked: a table entry that leaves 64
 // bits raises the trial's overflow flag instead of wrapping.
 //
 // Frontier domains.  A group processes B sources (<= 64) and T colourings.

@@ -1,5 +1,5 @@
 // Host planner: decomposition trees (Section 4.1), the tree-choice heuristic
-// (Section 5), aut(Q) (Preliminaries) and, per cycle block, the frontier
+// (Section 6), aut(Q) (Preliminaries) and, per cycle block, the frontier
 // program that the device executor runs for each group of sources.
 //
 // Cycle programs.  For a cycle block, the colourful matches are partitioned
@@ -262,7 +262,7 @@ static TreeScore score(const Tree &t) {
 }
 
 static bool better(const TreeScore &a, const TreeScore &b) {
-  // supported first; then the heuristic of Section 5; then a cycle root
+  // supported first; then the heuristic of Section 6; then a cycle root
   if (a.supported != b.supported) return a.supported > b.supported;
   if (a.longest != b.longest) return a.longest < b.longest;
   if (a.sumbd != b.sumbd) return a.sumbd < b.sumbd;

@@ -89,7 +89,7 @@ def test_planner_trees():
 
 
 def test_planner_heuristic_prefers_short_cycles():
-    """Section 5: the longest cycle block is the first criterion."""
+    """Section 6: the longest cycle block is the first criterion."""
     from paper_1602_04478_amd import cc
     # C_8 with chord (0,4): two 5-cycles, never the 8-cycle
     info = cc.Query(8, Q.cycle(8)[1] + [(0, 4)]).info()
