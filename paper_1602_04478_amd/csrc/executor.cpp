@@ -842,10 +842,16 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
     int64_t keys = is_edge_table(p_, (int)bi) ? g_.m2 : g_.n;
     launch_fill_u64(out, keys * Tg * C_out, st);
   }
+  static const bool progress = [] {
+    const char *v = getenv("CC_VERBOSE");
+    return v && atoi(v) >= 2;
+  }();
   // 1. dense groups: the sources with the widest reach
-  for (int64_t i = 0; i < ndense_; i += z_.B_dense)
+  for (int64_t i = 0; i < ndense_; i += z_.B_dense) {
     run_group(P, {d_src_.as<int32_t>() + i, sources_.data() + i, std::min<int64_t>(z_.B_dense, ndense_ - i), true}, Tg,
               out, C_out, prof);
+    if (progress) fprintf(stderr, "[cc] block %zu: dense group at source %lld enqueued\n", bi, (long long)i), fflush(stderr);
+  }
   // 2. one workgroup per source for the rest
   Light &L = light_[bi];
   if (!L.src.empty()) {
@@ -882,11 +888,15 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
   }
   // 3. grouped path for what the one-workgroup tier does not take
   if (!L.fails.empty()) {
-    for (int64_t i = 0; i < (int64_t)L.fails.size(); i += z_.B_sparse)
+    for (int64_t i = 0; i < (int64_t)L.fails.size(); i += z_.B_sparse) {
       run_group(P,
                 {L.d_fails.as<int32_t>() + i, L.fails.data() + i,
                  std::min<int64_t>(z_.B_sparse, (int64_t)L.fails.size() - i), fallback_dense_},
                 Tg, out, C_out, prof);
+      if (progress && (i / z_.B_sparse) % 32 == 0)
+        fprintf(stderr, "[cc] block %zu: sparse group at source %lld of %zu enqueued\n", bi, (long long)i,
+                L.fails.size()), fflush(stderr);
+    }
   }
 }
 
