@@ -486,6 +486,56 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
         n_scan += act ? (uint64_t)__popcll(below) : 0;
         uint64_t todo = __ballot(inb != 0);
         const bool stop = __ballot(vj == INT64_MAX) != 0;
+        // one trial: the neighbour's colour travels with it (loaded by its own lane)
+        const int cvj = (T == 1 && inb) ? colr[vj] : 0;
+        if (!ANN) {
+          // two neighbours per step, both rows' loads in flight together
+          while (todo) {
+            const int jA = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int jB = todo ? __builtin_ctzll(todo) : jA;
+            if (todo) todo &= todo - 1;
+            const bool hasB = jB != jA;
+            const int64_t vA = __shfl(vj, jA), vB = __shfl(vj, jB);
+            const uint64_t ibA = __shfl(inb, jA), ibB = __shfl(inb, jB);
+            const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA), mfB = grp.dense ? 0 : __shfl(mfull, jB);
+            const int64_t bA = grp.dense ? 0 : __shfl(bj, jA), bB = grp.dense ? 0 : __shfl(bj, jB);
+            int cA = __shfl(cvj, jA), cB = __shfl(cvj, jB);
+            bool okA = act && vA < u && ((ibA >> b) & 1ull);
+            bool okB = act && hasB && vB < u && ((ibB >> b) & 1ull);
+            if (T > 1) {
+              if (okA) cA = colr[(int64_t)lt * n + vA];
+              if (okB) cB = colr[(int64_t)lt * n + vB];
+            }
+            okA = okA && cA != cu && cA != cw;
+            okB = okB && cB != cu && cB != cw;
+            if (!okA && !okB) continue;
+            n_rows += (uint64_t)okA + (uint64_t)okB;
+            const uint64_t lowb = (1ull << b) - 1ull;
+            const uint64_t *rowA = a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & lowb)) * T + lt) * Ca;
+            const uint64_t *rowB = a.val + ((grp.dense ? vB * B + b : bB + __popcll(mfB & lowb)) * T + lt) * Ca;
+            for (int c0 = 0; c0 < Ca; c0 += 8) {
+              uint64_t xa[8], xb[8];
+#pragma unroll
+              for (int q = 0; q < 8; q++) {
+                xa[q] = okA && c0 + q < Ca ? rowA[c0 + q] : 0;
+                xb[q] = okB && c0 + q < Ca ? rowB[c0 + q] : 0;
+              }
+#pragma unroll
+              for (int q = 0; q < 8; q++) {
+                if (xa[q]) {
+                  const uint32_t R = spread2(s_um[c0 + q], cu, cA);
+                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * WAVE + lane], xa[q], of);
+                }
+                if (xb[q]) {
+                  const uint32_t R = spread2(s_um[c0 + q], cu, cB);
+                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cB), cu, cw)] * WAVE + lane], xb[q], of);
+                }
+              }
+            }
+          }
+          todo = 0;
+        }
         while (todo) {
           const int jj = __builtin_ctzll(todo);
           todo &= todo - 1;
@@ -495,8 +545,9 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
           const uint64_t ib = __shfl(inb, jj);
           const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj);
           const int64_t vb = grp.dense ? 0 : __shfl(bj, jj);
+          const int cvs = __shfl(cvj, jj);
           if (!act || v >= u || !((ib >> b) & 1ull)) continue;
-          const int cv = colr[(int64_t)lt * n + v];
+          const int cv = T == 1 ? cvs : colr[(int64_t)lt * n + v];
           if (cv == cu || cv == cw) continue;
           const int64_t id = grp.dense ? v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
           n_rows++;
