@@ -404,21 +404,38 @@ __global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uin
   }
 }
 
-// Vertex-major EdgeJoin: one wavefront per output vertex w, lane = (source b,
-// trial t).  All sources of the group share w's neighbour list, so each
-// neighbour v is read once per wave with its per-vertex bits (which sources
-// have an input row at v), and every lane then relaxes its own row (v, b) for
-// its trial into its own LDS column: no atomics, checked 64-bit adds.  The
-// lanes of one pass are the first 64 / T sources among w's output bits.
-template <bool ANN>
+// Vertex-major EdgeJoin.  A group of SW lanes (a whole wavefront, or a
+// quarter of one when few sources meet at a vertex) owns an output vertex w,
+// lane = (source b, trial t).  All sources of the group share w's neighbour
+// list, so each neighbour v is read once with its per-vertex bits (which
+// sources have an input row at v), and every lane then relaxes its own row
+// (v, b) for its trial into its own LDS column: no atomics, checked 64-bit
+// adds.  A pass takes the next SW / T sources among w's output bits.  Groups
+// talk only through ballots and shuffles inside the group, so groups of one
+// wavefront may follow different vertices.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {  // k < popcount(m)
+  int pos = 0;
+  for (int sh = 32; sh; sh >>= 1) {
+    const uint64_t lo = m & ((1ull << sh) - 1ull);
+    const int c = __popcll(lo);
+    if (k >= c) {
+      k -= c;
+      m >>= sh;
+      pos += sh;
+    } else {
+      m = lo;
+    }
+  }
+  return pos;
+}
+
+template <bool ANN, int SW>
 __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin,
                                               LevelDev Lout, RegDev a, RegDev dst, TabDev et, int e_src_first,
                                               uint32_t *ovf, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
   __shared__ int32_t s_src[WAVE];
-  __shared__ int8_t s_map[WAVE];  // pass slot -> source
-  __shared__ unsigned long long s_live;
   extern __shared__ uint64_t acc[];  // [C][64]: lane-owned columns
   load_rank(s_rank, lut);
   const int T = grp.T, B = grp.B, C = dst.C, Ca = a.C;
@@ -428,35 +445,41 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
   for (int c = lane; c < W; c += WAVE) s_um[c] = unrank(lut, ANN ? ro : ra, c);
   s_src[lane] = lane < B ? grp.src[lane] : -1;
   __syncthreads();
-  const int Bc = WAVE / T;             // sources per pass
-  const int lt = lane % T, lb = lane / T;  // lane's trial, its source's slot in the pass
+  constexpr int NG = WAVE / SW;  // groups per wavefront
+  const int gl = lane % SW, gbase = lane - gl;
+  const uint64_t gmask = SW == 64 ? ~0ull : ((1ull << SW) - 1ull);
+  auto gballot = [&](bool p) -> uint64_t { return ((uint64_t)__ballot(p) >> gbase) & gmask; };
+  const int Bc = SW / T;                 // sources per pass
+  const int lt = gl % T, lb = gl / T;    // lane's trial, its source's slot in the pass
   const int64_t n = g.n;
   uint64_t ofm = 0, n_scan = 0, n_rows = 0, n_ent = 0;
-  for (int64_t w = blockIdx.x; w < grp.n_lim; w += gridDim.x) {
-    // output rows at w: dense -- every source above w (sources descend); sparse -- the marks
-    const uint64_t ob = grp.dense ? (uint64_t)__ballot(lane < B && s_src[lane] > w) : Lout.m[w];
+  for (int64_t w = (int64_t)blockIdx.x * NG + lane / SW; w < grp.n_lim; w += (int64_t)gridDim.x * NG) {
+    // output rows at w: dense -- every source above w; sparse -- the marks
+    uint64_t ob = 0;
+    if (grp.dense) {
+      for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_src[i + gl] > w) << i;
+    } else {
+      ob = Lout.m[w];
+    }
     if (!ob) {
-      if (grp.dense && lane == 0) dst.mask[w] = 0;
+      if (grp.dense && gl == 0) dst.mask[w] = 0;
       continue;
     }
     const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
     const uint64_t obase = grp.dense ? 0 : Lout.base[w];
-    if (lane == 0) s_live = 0;
+    uint64_t live = 0;
     uint64_t rest = ob;
     while (rest) {
       // this pass: the first Bc sources of rest
-      const int rk = __popcll(rest & ((1ull << lane) - 1ull));
-      const bool mine = ((rest >> lane) & 1ull) && rk < Bc;
-      __syncthreads();
-      if (mine) s_map[rk] = (int8_t)lane;
-      const uint64_t pass = __ballot(mine);
+      const int nr = __popcll(rest);
+      const int np = nr < Bc ? nr : Bc;
+      const int last = nth_set_bit(rest, np - 1);
+      const uint64_t pass = last == 63 ? rest : rest & ((1ull << (last + 1)) - 1ull);
       rest &= ~pass;
-      __syncthreads();
-      const int np = __popcll(pass);
-      const int b = lb < np ? s_map[lb] : -1;
+      const int b = lb < np ? nth_set_bit(pass, lb) : -1;
       const int64_t u = b >= 0 ? s_src[b] : 0;
       int64_t umax = u;  // the neighbours below the pass's largest source
-      for (int o = 32; o > 0; o >>= 1) umax = max(umax, (int64_t)__shfl_xor(umax, o));
+      for (int o = SW / 2; o > 0; o >>= 1) umax = max(umax, (int64_t)__shfl_xor(umax, o, SW));
       int cu = 0, cw = 0;
       bool act = false;
       if (b >= 0) {
@@ -466,8 +489,8 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
       }
       for (int o = 0; o < C; o++) acc[o * WAVE + lane] = 0;
       bool of = false;
-      for (int64_t j0 = r0; j0 < r1; j0 += WAVE) {
-        const int64_t ee = j0 + lane;
+      for (int64_t j0 = r0; j0 < r1; j0 += SW) {
+        const int64_t ee = j0 + gl;
         int64_t vj = ee < r1 ? g.col[ee] : INT64_MAX;
         if (vj >= umax) vj = INT64_MAX;
         uint64_t inb = 0, mfull = 0;
@@ -482,10 +505,10 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
           }
           inb &= pass;
         }
-        const uint64_t below = __ballot(vj != INT64_MAX);
+        const uint64_t below = gballot(vj != INT64_MAX);
         n_scan += act ? (uint64_t)__popcll(below) : 0;
-        uint64_t todo = __ballot(inb != 0);
-        const bool stop = __ballot(vj == INT64_MAX) != 0;
+        uint64_t todo = gballot(inb != 0);
+        const bool stop = gballot(vj == INT64_MAX) != 0;
         // one trial: the neighbour's colour travels with it (loaded by its own lane)
         const int cvj = (T == 1 && inb) ? colr[vj] : 0;
         if (!ANN) {
@@ -496,11 +519,12 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
             const int jB = todo ? __builtin_ctzll(todo) : jA;
             if (todo) todo &= todo - 1;
             const bool hasB = jB != jA;
-            const int64_t vA = __shfl(vj, jA), vB = __shfl(vj, jB);
-            const uint64_t ibA = __shfl(inb, jA), ibB = __shfl(inb, jB);
-            const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA), mfB = grp.dense ? 0 : __shfl(mfull, jB);
-            const int64_t bA = grp.dense ? 0 : __shfl(bj, jA), bB = grp.dense ? 0 : __shfl(bj, jB);
-            int cA = __shfl(cvj, jA), cB = __shfl(cvj, jB);
+            // every lane of the group takes part in the cross-lane reads
+            const int64_t vA = __shfl(vj, jA, SW), vB = __shfl(vj, jB, SW);
+            const uint64_t ibA = __shfl(inb, jA, SW), ibB = __shfl(inb, jB, SW);
+            const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA, SW), mfB = grp.dense ? 0 : __shfl(mfull, jB, SW);
+            const int64_t bA = grp.dense ? 0 : __shfl(bj, jA, SW), bB = grp.dense ? 0 : __shfl(bj, jB, SW);
+            int cA = __shfl(cvj, jA, SW), cB = __shfl(cvj, jB, SW);
             bool okA = act && vA < u && ((ibA >> b) & 1ull);
             bool okB = act && hasB && vB < u && ((ibB >> b) & 1ull);
             if (T > 1) {
@@ -534,34 +558,21 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
               }
             }
           }
-          todo = 0;
-        }
-        while (todo) {
-          const int jj = __builtin_ctzll(todo);
-          todo &= todo - 1;
-          // every lane takes part in the cross-lane reads (a lane that is
-          // switched off cannot serve as a source)
-          const int64_t v = __shfl(vj, jj);
-          const uint64_t ib = __shfl(inb, jj);
-          const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj);
-          const int64_t vb = grp.dense ? 0 : __shfl(bj, jj);
-          const int cvs = __shfl(cvj, jj);
-          if (!act || v >= u || !((ib >> b) & 1ull)) continue;
-          const int cv = T == 1 ? cvs : colr[(int64_t)lt * n + v];
-          if (cv == cu || cv == cw) continue;
-          const int64_t id = grp.dense ? v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
-          n_rows++;
-          const uint64_t *row = a.val + (id * T + lt) * Ca;
-          if (!ANN) {
-            for (int c = 0; c < Ca; c++) {
-              const uint64_t x = row[c];
-              if (!x) continue;
-              const uint32_t R = spread2(s_um[c], cu, cv);
-              if ((R >> cw) & 1u) continue;
-              const int o = s_rank[squeeze2(R | (1u << cv), cu, cw)];
-              add_ck(acc[o * WAVE + lane], x, of);
-            }
-          } else {
+        } else {
+          while (todo) {
+            const int jj = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int64_t v = __shfl(vj, jj, SW);
+            const uint64_t ib = __shfl(inb, jj, SW);
+            const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj, SW);
+            const int64_t vb = grp.dense ? 0 : __shfl(bj, jj, SW);
+            const int cvs = __shfl(cvj, jj, SW);
+            if (!act || v >= u || !((ib >> b) & 1ull)) continue;
+            const int cv = T == 1 ? cvs : colr[(int64_t)lt * n + v];
+            if (cv == cu || cv == cw) continue;
+            const int64_t id = grp.dense ? v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
+            n_rows++;
+            const uint64_t *row = a.val + (id * T + lt) * Ca;
             const int64_t es = j0 + jj;
             const int64_t tslot = e_src_first ? g.rev[es] : es;
             const uint64_t *er = et.val + (tslot * T + lt) * et.C;
@@ -591,27 +602,24 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
       if (of) ofm |= 1ull << lt;
       // write the lane's row (w, b) for trial lt: sparse -- every marked row;
       // dense -- the rows nonzero in some trial (the others stay dead)
-      if (grp.dense) {
+      uint64_t mine = 0;
+      if (grp.dense && b >= 0) {
         bool nz = false;
-        if (b >= 0)
-          for (int o = 0; o < C; o++) nz |= acc[o * WAVE + lane] != 0;
-        if (nz) atomicOr(&s_live, 1ull << b);
-        __syncthreads();
+        for (int o = 0; o < C; o++) nz |= acc[o * WAVE + lane] != 0;
+        mine = nz ? 1ull << b : 0;
       }
-      if (b >= 0 && (!grp.dense || ((s_live >> b) & 1ull))) {
+      if (grp.dense)
+        for (int o = SW / 2; o > 0; o >>= 1) mine |= (uint64_t)__shfl_xor(mine, o, SW);
+      live |= mine;
+      if (b >= 0 && (!grp.dense || ((mine >> b) & 1ull))) {
         const int64_t id = grp.dense ? w * B + b : (int64_t)obase + __popcll(ob & ((1ull << b) - 1ull));
         uint64_t *drow = dst.val + (id * T + lt) * C;
         for (int o = 0; o < C; o++) drow[o] = acc[o * WAVE + lane];
       }
     }
-    if (grp.dense) {
-      __syncthreads();
-      if (lane == 0) {
-        dst.mask[w] = s_live;
-        n_ent += __popcll(s_live);
-      }
-    } else if (lane == 0) {
-      n_ent += __popcll(ob);
+    if (gl == 0) {
+      if (grp.dense) dst.mask[w] = live;
+      n_ent += __popcll(grp.dense ? live : ob);
     }
   }
   flag_trials(ovf, ofm);
@@ -1005,14 +1013,22 @@ void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, 
 void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
                RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st) {
   if (dst.C <= VMAX_C && (!etab.val || etab.C <= 256)) {
-    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(grp.n_lim, 32768));
     const size_t lds = (size_t)WAVE * dst.C * sizeof(uint64_t);
-    if (etab.val)
-      hipLaunchKernelGGL(k_ejv<true>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab,
-                         e_src_first, ovf, cur_lut());
-    else
-      hipLaunchKernelGGL(k_ejv<false>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab,
-                         e_src_first, ovf, cur_lut());
+    // sparse groups meet few sources per vertex: four vertices per wavefront
+    const bool quarter = !grp.dense && grp.T <= 16;
+    const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;
+    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(nw, 32768));
+#define CC_EJV(ANN_, SW_)                                                                                   \
+  hipLaunchKernelGGL((k_ejv<ANN_, SW_>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab, \
+                     e_src_first, ovf, cur_lut())
+    if (etab.val) {
+      if (quarter) CC_EJV(true, 16);
+      else CC_EJV(true, 64);
+    } else {
+      if (quarter) CC_EJV(false, 16);
+      else CC_EJV(false, 64);
+    }
+#undef CC_EJV
     return;
   }
   const int64_t N = grp.dense ? grp.n_lim * grp.B : (int64_t)1 << 62;
