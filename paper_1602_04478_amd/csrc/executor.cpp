@@ -387,19 +387,6 @@ double probe_copy(uint64_t bytes, int reps) {
   return 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
 }
 
-void dump_programs(const Plan &p) {
-    static const char *kn[] = {"INIT", "NJ", "EJ", "AXPY", "MROOT", "MU", "MV", "MEDGE", "MEDGE_T"};
-    for (size_t bi = 0; bi < p.programs.size(); bi++) {
-      const Program &P = p.programs[bi];
-      if (P.ops.empty()) continue;
-      fprintf(stderr, "[cc] block %zu program: %zu ops, %zu registers, depth %d\n", bi, P.ops.size(), P.reg_s.size(),
-              P.max_depth);
-      for (auto &o : P.ops)
-        fprintf(stderr, "[cc]   %-7s dst=%d(s%d,d%d) a=%d b=%d tab=%d ntab=%d w=%llu first=%d\n", kn[o.kind], o.dst,
-                o.dst >= 0 ? P.reg_s[o.dst] : -1, o.dst >= 0 ? P.reg_depth[o.dst] : -1, o.a, o.b, o.tab, o.ntab,
-                (unsigned long long)o.w, o.first);
-    }
-}
 
 uint64_t footprint(const DevGraph &g, const Plan &p, int trials, const ExecOptions &opt) {
   int T = std::min(std::max(trials, 1), 64);
@@ -446,6 +433,172 @@ double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::v
     return (double)((long double)q + (long double)r / (long double)d128);
   }
   return (double)(num / den);
+}
+
+// ------------------------------------------------------------------ fused schedule
+//
+// For the grouped path, a cycle program is regrouped into steps: a plain op,
+// or an EdgeJoin followed by the row-local ops (NodeJoin, AXPY, root merge)
+// that can run on its output vertex while the EdgeJoin row is in LDS.  A
+// register computed in such an epilogue is written to memory only if an op
+// after the step reads it.  An AXPY chain d = sum_k w_k x_k is rebuilt so that
+// a local term that dies there lends d its LDS block (scaled in place).
+struct EpiPlan {
+  std::vector<int> ops;      // NJ/MROOT op indices, or -1 - k for the k-th rebuilt AXPY
+  struct Axpy {
+    int dst, a;
+    uint64_t w;
+    int first;
+  };
+  std::vector<Axpy> axpy;
+  std::vector<int> regs;     // epilogue register -> program register (0: the EdgeJoin's output)
+  std::vector<int> col;      // LDS column of each epilogue register, -1: global
+  std::vector<int> write;
+  int ncols = 0;
+};
+struct Step {
+  int op;                    // the op (an EdgeJoin when fused)
+  bool fused = false;
+  EpiPlan epi;
+};
+
+static std::vector<Step> schedule(const Program &P, int k) {
+  const int n = (int)P.ops.size();
+  auto reads = [&](const Op &o, int r) {
+    if (o.a == r || (o.kind == OP_MROOT || o.kind == OP_MU || o.kind == OP_MV || o.kind == OP_MEDGE ||
+                     o.kind == OP_MEDGE_T) && o.b == r)
+      return true;
+    return o.kind == OP_AXPY && !o.first && o.dst == r;
+  };
+  auto used_from = [&](int r, int j) {
+    for (int q = j; q < n; q++)
+      if (reads(P.ops[q], r)) return true;
+    return false;
+  };
+  std::vector<char> mat(P.reg_s.size(), 0);  // in memory after the steps so far
+  std::vector<Step> out;
+  int i = 0;
+  while (i < n) {
+    const Op &op = P.ops[i];
+    if (op.kind != OP_EJ) {
+      out.push_back({i, false, {}});
+      if (op.dst >= 0) mat[op.dst] = 1;
+      i++;
+      continue;
+    }
+    const int depth = P.reg_depth[op.dst];
+    std::vector<char> loc(P.reg_s.size(), 0);
+    loc[op.dst] = 1;
+    int j = i + 1;
+    for (; j < n; j++) {
+      const Op &o = P.ops[j];
+      if (o.kind != OP_NJ && o.kind != OP_AXPY && o.kind != OP_MROOT) break;
+      auto avail = [&](int r) { return r >= 0 && (loc[r] || mat[r]); };
+      bool ok = avail(o.a);
+      if (o.kind == OP_MROOT) ok = ok && avail(o.b) && (loc[o.a] || loc[o.b]);
+      if (o.kind != OP_MROOT) ok = ok && P.reg_depth[o.dst] == depth && !mat[o.dst];
+      if (o.kind == OP_NJ) ok = ok && o.tab >= 0;
+      if (o.kind == OP_AXPY && !o.first) ok = ok && loc[o.dst];
+      if (ok && o.kind == OP_AXPY && o.first) {
+        // the chain is rebuilt here: every term must be ready now, and no op
+        // before its last link may read the partial sum
+        int last = j;
+        for (int q2 = j; q2 < n; q2++) {
+          const Op &o2 = P.ops[q2];
+          if (o2.kind != OP_NJ && o2.kind != OP_AXPY && o2.kind != OP_MROOT) break;
+          if (o2.kind == OP_AXPY && o2.dst == o.dst) last = q2;
+        }
+        for (int q2 = j; q2 <= last && ok; q2++) {
+          const Op &o2 = P.ops[q2];
+          if (o2.kind == OP_AXPY && o2.dst == o.dst) ok = avail(o2.a) && !(q2 > j && o2.first);
+          else ok = !reads(o2, o.dst);
+        }
+      }
+      if (!ok) break;
+      if (o.kind != OP_MROOT) loc[o.dst] = 1;
+    }
+    Step stp{i, j > i + 1, {}};
+    if (!stp.fused) {
+      out.push_back(stp);
+      mat[op.dst] = 1;
+      i++;
+      continue;
+    }
+    EpiPlan &E = stp.epi;
+    auto reg_of = [&](int r) {
+      for (size_t q = 0; q < E.regs.size(); q++)
+        if (E.regs[q] == r) return (int)q;
+      E.regs.push_back(r);
+      E.col.push_back(-1);
+      E.write.push_back(0);
+      return (int)E.regs.size() - 1;
+    };
+    auto new_block = [&](int e) {
+      E.col[e] = E.ncols;
+      E.ncols += (int)slots_pair(k, P.reg_s[E.regs[e]]);
+    };
+    new_block(reg_of(op.dst));
+    // registers that leave the step
+    auto leaves = [&](int r) { return used_from(r, j); };
+    for (int q = i + 1; q < j; q++) {
+      const Op &o = P.ops[q];
+      if (o.kind == OP_NJ || o.kind == OP_MROOT) {
+        if (o.kind == OP_NJ) new_block(reg_of(o.dst));
+        reg_of(o.a);
+        if (o.kind == OP_MROOT) reg_of(o.b);
+        E.ops.push_back(q);
+        continue;
+      }
+      // AXPY: a chain building o.dst from here
+      if (!o.first) {  // a later link of a chain already rebuilt
+        continue;
+      }
+      std::vector<std::pair<int, uint64_t>> terms;  // (register, weight)
+      int last = q;
+      for (int q2 = q; q2 < j; q2++) {
+        const Op &o2 = P.ops[q2];
+        if (o2.kind == OP_AXPY && o2.dst == o.dst) {
+          terms.push_back({o2.a, o2.w});
+          last = q2;
+        }
+      }
+      // a local term that dies here lends its block
+      int lend = -1;
+      for (size_t t = 0; t < terms.size() && lend < 0; t++) {
+        const int r = terms[t].first;
+        if (!loc[r] || leaves(r)) continue;
+        bool later = false;
+        for (int q3 = last + 1; q3 < j; q3++) later |= reads(P.ops[q3], r);
+        for (size_t t2 = 0; t2 < terms.size(); t2++) later |= t2 != t && terms[t2].first == r;
+        if (!later) lend = (int)t;
+      }
+      const int d = reg_of(o.dst);
+      if (lend >= 0) {
+        const int x = reg_of(terms[lend].first);
+        E.col[d] = E.col[x];
+        E.axpy.push_back({d, x, terms[lend].second, 1});
+      } else {
+        new_block(d);
+        E.axpy.push_back({d, reg_of(terms[0].first), terms[0].second, 1});
+      }
+      E.ops.push_back(-1 - (int)(E.axpy.size() - 1));
+      for (size_t t = 0; t < terms.size(); t++) {
+        if ((int)t == (lend >= 0 ? lend : 0)) continue;
+        E.axpy.push_back({d, reg_of(terms[t].first), terms[t].second, 0});
+        E.ops.push_back(-1 - (int)(E.axpy.size() - 1));
+      }
+    }
+    for (size_t e = 0; e < E.regs.size(); e++) {
+      const int r = E.regs[e];
+      if (E.col[e] >= 0 && leaves(r)) {
+        E.write[e] = 1;
+        mat[r] = 1;
+      }
+    }
+    out.push_back(stp);
+    i = j;
+  }
+  return out;
 }
 
 // ------------------------------------------------------------------ solver
@@ -706,11 +859,37 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
   hipStream_t st = st_;
   const uint8_t *colr = d_col_.as<uint8_t>();
   uint32_t *ovf = d_ovf_.as<uint32_t>();
-  // NodeJoin outputs keep their input's activity mask
+  // the steps: with CC_FUSE=1, EdgeJoins with their row-local followers fused
+  // where the epilogue fits.  Off by default: the fused epilogue runs one lane
+  // per row through every slot, and on the 1e6-vertex workload that costs more
+  // (5.2 s per colouring) than the separate flat passes it replaces (3.5 s).
+  const char *fuse_env = getenv("CC_FUSE");
+  const bool fuse_on = fuse_env && *fuse_env == '1';
+  std::vector<Step> steps;
+  if (fuse_on) {
+    steps = schedule(P, k);
+  } else {
+    for (size_t i = 0; i < P.ops.size(); i++) steps.push_back({(int)i, false, {}});
+  }
+  std::vector<Step> flat;
+  for (auto &stp : steps) {
+    const Op &op = P.ops[stp.op];
+    const int ce = op.tab >= 0 ? table_C(p_, op.tab) : 0;
+    if (stp.fused && !epi_fits(stp.epi.ncols, Tg, ce)) {
+      // run the step's ops one by one: every op from the EdgeJoin up to the next step
+      const size_t nx = (size_t)(&stp - steps.data()) + 1;
+      const int end = nx < steps.size() ? steps[nx].op : (int)P.ops.size();
+      for (int q = stp.op; q < end; q++) flat.push_back({q, false, {}});
+    } else {
+      flat.push_back(stp);
+    }
+  }
+  steps.swap(flat);
+  // NodeJoin outputs of unfused NodeJoins keep their input's activity mask
   std::vector<int> mown(P.reg_s.size());
   for (size_t r = 0; r < mown.size(); r++) mown[r] = (int)r;
-  for (auto &op : P.ops)
-    if (op.kind == OP_NJ) mown[op.dst] = mown[op.a];
+  for (auto &stp : steps)
+    if (!stp.fused && P.ops[stp.op].kind == OP_NJ) mown[P.ops[stp.op].dst] = mown[P.ops[stp.op].a];
   auto regdev = [&](int r) {
     RegDev d;
     d.val = regs_[r].val.as<uint64_t>();
@@ -747,13 +926,58 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
     if (prof) prof->end();
     built[d] = 1;
   };
-  for (size_t oi = 0; oi < P.ops.size(); oi++) {
-    const Op &op = P.ops[oi];
+  for (const Step &stp : steps) {
+    const Op &op = P.ops[stp.op];
     static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
                                   "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
     if (op.kind == OP_INIT) build(1);
     if (op.kind == OP_EJ) build(P.reg_depth[op.dst]);
     grp.prof = nullptr;
+    if (stp.fused) {
+      const EpiPlan &E = stp.epi;
+      Epilogue epi{};
+      epi.nregs = (int)E.regs.size();
+      epi.ncols = E.ncols;
+      double out_slots = 0;  // per entry and trial: rows written and global rows read
+      for (size_t e = 0; e < E.regs.size(); e++) {
+        RegDev d = regdev(E.regs[e]);
+        if (E.col[e] >= 0) d.mask = regs_[E.regs[e]].mask.as<uint64_t>();
+        epi.regs[e] = EpiReg{d, lv(E.regs[e]), E.col[e], E.write[e]};
+        if (E.write[e] || E.col[e] < 0) out_slots += d.C;
+      }
+      auto idx = [&](int r) {
+        for (size_t e = 0; e < E.regs.size(); e++)
+          if (E.regs[e] == r) return (int)e;
+        fail(CC_E_DEVICE, "fused step refers to a register it does not hold");
+        return 0;
+      };
+      for (int q : E.ops) {
+        EpiOp eo{};
+        if (q < 0) {
+          const EpiPlan::Axpy &x = E.axpy[-1 - q];
+          eo = EpiOp{EPI_AXPY, x.dst, x.a, -1, TabDev{nullptr, 0, 0}, x.w, x.first};
+        } else {
+          const Op &o = P.ops[q];
+          if (o.kind == OP_NJ) {
+            eo = EpiOp{EPI_NJ, idx(o.dst), idx(o.a), -1, tabdev(o.tab), 1, 0};
+            out_slots += table_C(p_, o.tab);
+          } else {
+            eo = EpiOp{EPI_MROOT, -1, idx(o.a), idx(o.b), TabDev{nullptr, 0, 0}, o.w, 0};
+          }
+        }
+        epi.ops[epi.nops++] = eo;
+      }
+      if (prof) {
+        std::string nm = std::string("edgejoin") + (G.dense ? "_dense" : "_sparse");
+        const double Cin = (double)slots_pair(k, P.reg_s[op.a]);
+        const double Ce = op.tab >= 0 ? (double)table_C(p_, op.tab) : 0.0;
+        grp.prof = prof->begin(nm.c_str(), true, 4.0, 8.0 * (Cin + Ce), 8.0 * Tg * out_slots);
+      }
+      launch_ej_epi(gd_, grp, colr, lv(op.a), regdev(op.a), epi, tabdev(op.tab), op.tab_src_first, ovf, acc_, st);
+      HIP_CHECK(hipGetLastError());
+      if (prof) prof->end();
+      continue;
+    }
     if (prof) {
       std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
       if (op.kind == OP_EJ) {
@@ -1073,6 +1297,43 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
   }
   g_last_tune = rep;
   return res;
+}
+
+void dump_programs(const Plan &p) {
+    static const char *kn[] = {"INIT", "NJ", "EJ", "AXPY", "MROOT", "MU", "MV", "MEDGE", "MEDGE_T"};
+    for (size_t bi = 0; bi < p.programs.size(); bi++) {
+      const Program &P = p.programs[bi];
+      if (P.ops.empty()) continue;
+      fprintf(stderr, "[cc] block %zu program: %zu ops, %zu registers, depth %d\n", bi, P.ops.size(), P.reg_s.size(),
+              P.max_depth);
+      for (auto &o : P.ops)
+        fprintf(stderr, "[cc]   %-7s dst=%d(s%d,d%d) a=%d b=%d tab=%d ntab=%d w=%llu first=%d\n", kn[o.kind], o.dst,
+                o.dst >= 0 ? P.reg_s[o.dst] : -1, o.dst >= 0 ? P.reg_depth[o.dst] : -1, o.a, o.b, o.tab, o.ntab,
+                (unsigned long long)o.w, o.first);
+    }
+  for (size_t bi = 0; bi < p.programs.size(); bi++) {
+    const Program &P = p.programs[bi];
+    if (P.ops.empty()) continue;
+    for (auto &stp : schedule(P, p.k)) {
+      if (!stp.fused) {
+        fprintf(stderr, "[cc] step op %d\n", stp.op);
+        continue;
+      }
+      fprintf(stderr, "[cc] step op %d fused: %zu epilogue ops, %d LDS columns; regs", stp.op, stp.epi.ops.size(),
+              stp.epi.ncols);
+      for (size_t e = 0; e < stp.epi.regs.size(); e++)
+        fprintf(stderr, " r%d(col %d%s)", stp.epi.regs[e], stp.epi.col[e], stp.epi.write[e] ? ",w" : "");
+      fprintf(stderr, "\n");
+      for (int q : stp.epi.ops) {
+        if (q < 0) {
+          auto &x = stp.epi.axpy[-1 - q];
+          fprintf(stderr, "[cc]     AXPY e%d %s= %llu * e%d\n", x.dst, x.first ? "" : "+", (unsigned long long)x.w, x.a);
+        } else {
+          fprintf(stderr, "[cc]     op %d\n", q);
+        }
+      }
+    }
+  }
 }
 
 }  // namespace cc

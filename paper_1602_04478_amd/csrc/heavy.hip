@@ -429,15 +429,35 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {  // k < popcount
   return pos;
 }
 
-template <bool ANN, int SW>
-__global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin,
-                                              LevelDev Lout, RegDev a, RegDev dst, TabDev et, int e_src_first,
-                                              uint32_t *ovf, const uint16_t *lut) {
+// dynamic LDS of k_ejv: lane-owned columns, then (with an epilogue) the
+// operands' rows, the unrank lists and the root-merge sums
+__host__ __device__ constexpr size_t ejv_lds(int ncols, int nregs, bool epi) {
+  return (size_t)ncols * WAVE * 8 + (epi ? (size_t)nregs * WAVE * 8 + (LUT_SIZE - LUT_UNRANK) * 2 + 2 * WAVE * 8 : 0);
+}
+
+template <bool ANN, int SW, bool EPI>
+__global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
+                                              const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
+                                              AccDev accd, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
   __shared__ int32_t s_src[WAVE];
-  extern __shared__ uint64_t acc[];  // [C][64]: lane-owned columns
+  __shared__ uint64_t s_live[EPI_MAX_REGS * (WAVE / SW)];  // dense: per written register and group, live rows
+  extern __shared__ uint64_t accs[];  // [columns][64]: lane-owned columns, EdgeJoin output first
+  int64_t *const s_rid = (int64_t *)(accs + (size_t)epi.ncols * WAVE);  // [regs][64] operands' rows
+  uint16_t *const s_unr = (uint16_t *)(s_rid + (size_t)epi.nregs * WAVE);  // unrank lists and offsets
+  uint64_t *const s_msum = (uint64_t *)(s_unr + (LUT_SIZE - LUT_UNRANK));  // [64] x (lo, hi)
   load_rank(s_rank, lut);
+  if (EPI) {
+    s_msum[threadIdx.x] = 0;
+    s_msum[threadIdx.x + WAVE] = 0;
+    for (int i = threadIdx.x; i < LUT_SIZE - LUT_UNRANK; i += WAVE) s_unr[i] = lut[LUT_UNRANK + i];
+  }
+  // unranked slot idx of rank r from the LDS copy (layout of the global table, shifted)
+  auto unr = [&](int r, int idx) -> uint32_t { return s_unr[s_unr[LUT_OFF - LUT_UNRANK + r] + idx]; };
+  const LevelDev Lout = epi.regs[0].L;
+  const RegDev dst = epi.regs[0].r;
+  uint64_t *const acc = accs + (size_t)epi.regs[0].col * WAVE;
   const int T = grp.T, B = grp.B, C = dst.C, Ca = a.C;
   const int ra = a.s - 2, ro = dst.s - 2;
   const int W = ANN ? C : Ca;
@@ -452,7 +472,9 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
   const int Bc = SW / T;                 // sources per pass
   const int lt = gl % T, lb = gl / T;    // lane's trial, its source's slot in the pass
   const int64_t n = g.n;
+  const uint32_t Kmask = (1u << grp.k) - 1u;
   uint64_t ofm = 0, n_scan = 0, n_rows = 0, n_ent = 0;
+  uint64_t mlo = 0, mhi = 0;  // this lane's root-merge sum (its trial)
   for (int64_t w = (int64_t)blockIdx.x * NG + lane / SW; w < grp.n_lim; w += (int64_t)gridDim.x * NG) {
     // output rows at w: dense -- every source above w; sparse -- the marks
     uint64_t ob = 0;
@@ -462,12 +484,14 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
       ob = Lout.m[w];
     }
     if (!ob) {
-      if (grp.dense && gl == 0) dst.mask[w] = 0;
+      if (grp.dense && gl == 0)
+        for (int j = 0; j < epi.nregs; j++)
+          if (epi.regs[j].write) epi.regs[j].r.mask[w] = 0;
       continue;
     }
     const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
-    const uint64_t obase = grp.dense ? 0 : Lout.base[w];
-    uint64_t live = 0;
+    if (grp.dense && gl == 0)
+      for (int j = 0; j < epi.nregs; j++) s_live[j * NG + lane / SW] = 0;
     uint64_t rest = ob;
     while (rest) {
       // this pass: the first Bc sources of rest
@@ -487,7 +511,7 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
         cw = colr[(int64_t)lt * n + w];
         act = cu != cw;
       }
-      for (int o = 0; o < C; o++) acc[o * WAVE + lane] = 0;
+      for (int o = 0; o < epi.ncols; o++) accs[o * WAVE + lane] = 0;
       bool of = false;
       for (int64_t j0 = r0; j0 < r1; j0 += SW) {
         const int64_t ee = j0 + gl;
@@ -599,30 +623,121 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
         }
         if (stop) break;
       }
-      if (of) ofm |= 1ull << lt;
-      // write the lane's row (w, b) for trial lt: sparse -- every marked row;
-      // dense -- the rows nonzero in some trial (the others stay dead)
-      uint64_t mine = 0;
-      if (grp.dense && b >= 0) {
-        bool nz = false;
-        for (int o = 0; o < C; o++) nz |= acc[o * WAVE + lane] != 0;
-        mine = nz ? 1ull << b : 0;
+      // epilogue: row-local ops on the rows of w, operands in LDS or read
+      // from global memory at their own level
+      if (EPI && b >= 0 && epi.nops) {
+        for (int j = 0; j < epi.nregs; j++) {
+          const EpiReg &R = epi.regs[j];
+          int64_t id = -1;
+          if (R.col < 0) {
+            if (grp.dense) id = ((R.r.mask[w] >> b) & 1ull) ? w * B + b : -1;
+            else id = sparse_entry(R.L, w, b);
+          }
+          s_rid[j * WAVE + lane] = id;
+        }
+        auto val = [&](int j, int slot) -> uint64_t {
+          const EpiReg &R = epi.regs[j];
+          if (R.col >= 0) return accs[(R.col + slot) * WAVE + lane];
+          const int64_t id = s_rid[j * WAVE + lane];
+          return id < 0 ? 0 : R.r.val[(id * T + lt) * R.r.C + slot];
+        };
+        for (int oi = 0; oi < epi.nops; oi++) {
+          const EpiOp &op = epi.ops[oi];
+          if (op.kind == EPI_NJ) {
+            // dst[R'] = sum over splits R' = R + Ra of a[R] * A[w][Ra]  (NodeJoin at w)
+            const EpiReg &D = epi.regs[op.dst];
+            const int rA = op.nt.s - 1;
+            for (int c = 0; c < D.r.C; c++) {
+              uint64_t v = 0;
+              if (cu != cw) {
+                const uint32_t Rp = spread2(unr(D.r.s - 2, c), cu, cw);
+                const uint64_t *nr = op.nt.val + (w * T + lt) * op.nt.C;
+                uint32_t sA = Rp;
+                for (;;) {
+                  if (__popc(sA) == rA) {
+                    const uint64_t y = nr[s_rank[squeeze1(sA, cw)]];
+                    if (y) {
+                      const uint64_t x = val(op.a, s_rank[squeeze2(Rp & ~sA, cu, cw)]);
+                      if (x) add_ck(v, mul_ck(x, y, of), of);
+                    }
+                  }
+                  if (sA == 0) break;
+                  sA = (sA - 1) & Rp;
+                }
+              }
+              accs[(D.col + c) * WAVE + lane] = v;
+            }
+          } else if (op.kind == EPI_AXPY) {
+            const EpiReg &D = epi.regs[op.dst];
+            for (int c = 0; c < D.r.C; c++) {
+              uint64_t y = op.first ? 0 : accs[(D.col + c) * WAVE + lane];
+              const uint64_t x = val(op.a, c);
+              if (x) add_ck(y, mul_ck(op.w, x, of), of);
+              accs[(D.col + c) * WAVE + lane] = y;
+            }
+          } else if (cu != cw) {  // EPI_MROOT: the cycle closes at w
+            const EpiReg &A = epi.regs[op.a];
+            for (int c = 0; c < A.r.C; c++) {
+              const uint64_t x = val(op.a, c);
+              if (!x) continue;
+              const uint32_t R1 = spread2(unr(A.r.s - 2, c), cu, cw);
+              const uint32_t R2 = Kmask & ~R1 & ~(1u << cu) & ~(1u << cw);
+              const uint64_t y = val(op.b, s_rank[squeeze2(R2, cu, cw)]);
+              if (!y) continue;
+              uint64_t pl = x * y, ph = __umul64hi(x, y);
+              if (op.w != 1) {
+                const uint64_t l2 = pl * op.w, c2 = __umul64hi(pl, op.w);
+                const uint64_t h2 = ph * op.w + c2;
+                if (__umul64hi(ph, op.w) != 0 || h2 < c2) of = true;
+                pl = l2;
+                ph = h2;
+              }
+              if (accd.per_src) atomic_add128(&accd.per_src[2 * (u * T + lt)], pl, ph);
+              const uint64_t sl = mlo + pl;
+              mhi += ph + (sl < pl ? 1u : 0u);
+              mlo = sl;
+            }
+          }
+        }
       }
-      if (grp.dense)
-        for (int o = SW / 2; o > 0; o >>= 1) mine |= (uint64_t)__shfl_xor(mine, o, SW);
-      live |= mine;
-      if (b >= 0 && (!grp.dense || ((mine >> b) & 1ull))) {
-        const int64_t id = grp.dense ? w * B + b : (int64_t)obase + __popcll(ob & ((1ull << b) - 1ull));
-        uint64_t *drow = dst.val + (id * T + lt) * C;
-        for (int o = 0; o < C; o++) drow[o] = acc[o * WAVE + lane];
+      if (of) ofm |= 1ull << lt;
+      // write the registers that leave the vertex, the lane's row (w, b) for
+      // trial lt: sparse -- every marked row; dense -- the rows nonzero in some
+      // trial (the others stay dead)
+      for (int j = 0; j < epi.nregs; j++) {
+        const EpiReg &R = epi.regs[j];
+        if (!R.write) continue;
+        const int Cj = R.r.C;
+        uint64_t mine = 0;
+        if (grp.dense && b >= 0) {
+          bool nz = false;
+          for (int o = 0; o < Cj; o++) nz |= accs[(R.col + o) * WAVE + lane] != 0;
+          mine = nz ? 1ull << b : 0;
+        }
+        if (grp.dense)
+          for (int o = SW / 2; o > 0; o >>= 1) mine |= (uint64_t)__shfl_xor(mine, o, SW);
+        if (grp.dense && gl == 0) s_live[j * NG + lane / SW] |= mine;
+        if (b >= 0 && (!grp.dense || ((mine >> b) & 1ull))) {
+          const int64_t id = grp.dense ? w * B + b : sparse_entry(R.L, w, b);
+          uint64_t *drow = R.r.val + (id * T + lt) * Cj;
+          for (int o = 0; o < Cj; o++) drow[o] = accs[(R.col + o) * WAVE + lane];
+        }
       }
     }
     if (gl == 0) {
-      if (grp.dense) dst.mask[w] = live;
-      n_ent += __popcll(grp.dense ? live : ob);
+      if (grp.dense)
+        for (int j = 0; j < epi.nregs; j++)
+          if (epi.regs[j].write) epi.regs[j].r.mask[w] = s_live[j * NG + lane / SW];
+      n_ent += __popcll(ob);
     }
   }
   flag_trials(ovf, ofm);
+  if (EPI) {
+    if (mlo | mhi) atomic_add128(&s_msum[2 * lt], mlo, mhi);
+    __syncthreads();
+    if (lane < T && (s_msum[2 * lane] | s_msum[2 * lane + 1]))
+      atomic_add128(&accd.sum[2 * lane], s_msum[2 * lane], s_msum[2 * lane + 1]);
+  }
   if (grp.prof) {
     for (int o = 32; o > 0; o >>= 1) {
       n_scan += __shfl_xor(n_scan, o);
@@ -1010,25 +1125,44 @@ void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, 
                      ntab, ovf, cur_lut());
 }
 
+bool epi_fits(int ncols, int T, int etab_C) {
+  return ncols <= VMAX_C && T <= WAVE && etab_C <= 256 && ejv_lds(ncols, EPI_MAX_REGS, true) <= 56 * 1024;
+}
+
+void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
+                   const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st) {
+  const bool ep = epi.nops > 0;
+  const size_t lds = ejv_lds(epi.ncols, epi.nregs, ep);
+  // sparse groups meet few sources per vertex: four vertices per wavefront
+  const bool quarter = !grp.dense && grp.T <= 16;
+  const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;
+  const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(nw, 32768));
+#define CC_EJV(ANN_, SW_, EPI_)                                                                             \
+  hipLaunchKernelGGL((k_ejv<ANN_, SW_, EPI_>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, a, epi, etab, \
+                     e_src_first, ovf, acc, cur_lut())
+  const int sel = (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
+  switch (sel) {
+    case 0: CC_EJV(false, 64, false); break;
+    case 1: CC_EJV(false, 64, true); break;
+    case 2: CC_EJV(false, 16, false); break;
+    case 3: CC_EJV(false, 16, true); break;
+    case 4: CC_EJV(true, 64, false); break;
+    case 5: CC_EJV(true, 64, true); break;
+    case 6: CC_EJV(true, 16, false); break;
+    default: CC_EJV(true, 16, true); break;
+  }
+#undef CC_EJV
+}
+
 void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
                RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st) {
-  if (dst.C <= VMAX_C && (!etab.val || etab.C <= 256)) {
-    const size_t lds = (size_t)WAVE * dst.C * sizeof(uint64_t);
-    // sparse groups meet few sources per vertex: four vertices per wavefront
-    const bool quarter = !grp.dense && grp.T <= 16;
-    const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;
-    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(nw, 32768));
-#define CC_EJV(ANN_, SW_)                                                                                   \
-  hipLaunchKernelGGL((k_ejv<ANN_, SW_>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab, \
-                     e_src_first, ovf, cur_lut())
-    if (etab.val) {
-      if (quarter) CC_EJV(true, 16);
-      else CC_EJV(true, 64);
-    } else {
-      if (quarter) CC_EJV(false, 16);
-      else CC_EJV(false, 64);
-    }
-#undef CC_EJV
+  if (epi_fits(dst.C, grp.T, etab.val ? etab.C : 0)) {
+    Epilogue epi{};
+    epi.nops = 0;
+    epi.nregs = 1;
+    epi.ncols = dst.C;
+    epi.regs[0] = EpiReg{dst, Lout, 0, 1};
+    launch_ej_epi(g, grp, colr, Lin, a, epi, etab, e_src_first, ovf, AccDev{nullptr, nullptr, nullptr}, st);
     return;
   }
   const int64_t N = grp.dense ? grp.n_lim * grp.B : (int64_t)1 << 62;

@@ -77,6 +77,31 @@ struct AccDev {
   uint64_t *per_src;   // optional [n][T] x (lo, hi) by rank, or null
 };
 
+// Row-local ops fused after a vertex-major EdgeJoin: they run on the rows of
+// the output vertex while its EdgeJoin row is still in LDS.  Operands are
+// registers of the epilogue: register 0 is the EdgeJoin's output; a register
+// with an LDS block lives in LDS (and is written out when `write` is set); a
+// register without one is read from global memory at its own level.
+enum EpiKind { EPI_NJ = 0, EPI_AXPY = 1, EPI_MROOT = 2 };
+constexpr int EPI_MAX_OPS = 8, EPI_MAX_REGS = 8;
+struct EpiReg {
+  RegDev r;        // global storage (val unused for an LDS-only register)
+  LevelDev L;      // its level (rows are found there when read from global memory)
+  int col;         // first LDS column of its block, or -1
+  int write;       // 1: written to r at the end of the vertex
+};
+struct EpiOp {
+  int kind, dst, a, b;  // register indices (dst unused for MROOT)
+  TabDev nt;            // NodeJoin's node table
+  uint64_t w;           // AXPY / MROOT weight
+  int first;            // AXPY: dst starts at zero
+};
+struct Epilogue {
+  int nops, nregs, ncols;
+  EpiOp ops[EPI_MAX_OPS];
+  EpiReg regs[EPI_MAX_REGS];
+};
+
 const uint16_t *lut_device(int device);
 // trials x slots of one frontier row: EdgeJoin keeps two accumulator words per
 // slot in LDS, within 64 KiB per workgroup with its rank tables
@@ -104,6 +129,10 @@ void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, 
                  LevelDev L, RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st);
 void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
                RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st);
+// EdgeJoin with a fused epilogue (vertex-major kernel only; see epi_fits)
+void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
+                   const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st);
+bool epi_fits(int ncols, int T, int etab_C);
 void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev L, RegDev a, RegDev dst,
                TabDev ntab, uint32_t *ovf, hipStream_t st);
 void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,
