@@ -926,7 +926,9 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
     if (prof) prof->end();
     built[d] = 1;
   };
+  size_t skip_until = 0;  // steps folded into an earlier launch
   for (const Step &stp : steps) {
+    if ((size_t)(&stp - steps.data()) < skip_until) continue;
     const Op &op = P.ops[stp.op];
     static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
                                   "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
@@ -1009,9 +1011,29 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
         launch_ej(gd_, grp, colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst), tabdev(op.tab),
                   op.tab_src_first, ovf, st);
         break;
-      case OP_AXPY:
+      case OP_AXPY: {
+        // a chain dst = w1 a1 + w2 a2 + ... in the next steps runs as one pass
+        size_t si = (size_t)(&stp - steps.data());
+        if (op.first) {
+          std::vector<RegDev> ta{regdev(op.a)};
+          std::vector<uint64_t> tw{op.w};
+          size_t sj = si + 1;
+          while (sj < steps.size() && ta.size() < 4 && !steps[sj].fused) {
+            const Op &o2 = P.ops[steps[sj].op];
+            if (o2.kind != OP_AXPY || o2.first || o2.dst != op.dst || o2.a == op.dst) break;
+            ta.push_back(regdev(o2.a));
+            tw.push_back(o2.w);
+            sj++;
+          }
+          if (ta.size() > 1) {
+            launch_axpyn(grp, lv(op.a), ta.data(), tw.data(), (int)ta.size(), regdev(op.dst), ovf, st);
+            skip_until = sj;
+            break;
+          }
+        }
         launch_axpy(grp, lv(op.a), regdev(op.a), regdev(op.dst), op.w, op.first, ovf, st);
         break;
+      }
       case OP_MROOT:
         launch_mroot(grp, g_.n, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), op.w, acc_, st);
         break;

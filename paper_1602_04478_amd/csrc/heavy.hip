@@ -823,6 +823,39 @@ __global__ __launch_bounds__(BLK) void k_axpy(GroupDev grp, LevelDev L, RegDev a
   flag_trials(ovf, ofm);
 }
 
+// dst = sum of w_i * a_i over up to four terms (an AXPY chain in one pass)
+struct AxpyTerms {
+  RegDev a[4];
+  uint64_t w[4];
+  int n;
+};
+__global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, LevelDev L, AxpyTerms tm, RegDev dst, uint32_t *ovf) {
+  const int T = grp.T, C = dst.C;
+  const int64_t per = (int64_t)T * C;
+  const int64_t N = nentries(grp, L) * per;
+  uint64_t ofm = 0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
+    bool of = false;
+    uint64_t y = 0;
+    const int64_t row = i / per;
+    for (int q = 0; q < tm.n; q++) {
+      if (grp.dense && !((tm.a[q].mask[row / grp.B] >> (row % grp.B)) & 1ull)) continue;
+      const uint64_t x = tm.a[q].val[i];
+      if (x) add_ck(y, mul_ck(tm.w[q], x, of), of);
+    }
+    dst.val[i] = y;
+    if (of) ofm |= 1ull << ((i / C) % T);
+  }
+  flag_trials(ovf, ofm);
+}
+__global__ void k_mask_orn(AxpyTerms tm, uint64_t *dm, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t m = 0;
+    for (int q = 0; q < tm.n; q++) m |= tm.a[q].mask[i];
+    dm[i] = m;
+  }
+}
+
 // dst.mask = (first ? 0 : dst.mask) | a.mask
 __global__ void k_mask_or(const uint64_t *am, uint64_t *dm, int64_t n, int first) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -840,20 +873,16 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
                                                LevelDev Lb, RegDev a, RegDev bb, uint64_t w, AccDev acc,
                                                const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_ua[256];  // unranked slots of a
   __shared__ uint64_t s_acc[2 * 64];
   for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) s_acc[i] = 0;
   load_rank(s_rank, lut);
   const int T = grp.T, Ca = a.C, Cb = bb.C, k = grp.k;
+  for (int c = threadIdx.x; c < Ca; c += BLK) s_ua[c] = unrank(lut, a.s - 2, c);
+  __syncthreads();
   const uint32_t Kmask = (1u << k) - 1u;
-  const int64_t per = (int64_t)T * Ca;
-  const int64_t N = nentries(grp, La) * per;
-  uint64_t lo0 = 0, hi0 = 0;
-  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
-    const int64_t e = i / per;
-    if (grp.dense && !((a.mask[e / grp.B] >> (e % grp.B)) & 1ull)) continue;
-    const uint64_t x = a.val[i];
-    if (!x) continue;
-    const int r = (int)(i - e * per), t = r / Ca, c = r - t * Ca;
+  const int64_t N = nentries(grp, La);
+  for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < N; e += (int64_t)gridDim.x * BLK) {
     int64_t v;
     int b;
     entry_vb(grp, La, e, v, b);
@@ -861,30 +890,38 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
     const int64_t eb = row_of(grp, Lb, bb, v, b);
     if (eb < 0) continue;
     const int64_t u = grp.src[b];
-    const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
-    if (cu == cv) continue;
-    const uint32_t R1 = spread2(unrank(lut, a.s - 2, c), cu, cv);
-    const uint32_t R2 = Kmask & ~R1 & ~(1u << cu) & ~(1u << cv);
-    const uint64_t y = bb.val[(eb * T + t) * Cb + s_rank[squeeze2(R2, cu, cv)]];
-    if (!y) continue;
-    uint64_t pl = x * y, ph = __umul64hi(x, y);
-    if (w != 1) {
-      uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
-      uint64_t h2 = ph * w + c2;
-      if (__umul64hi(ph, w) != 0 || h2 < c2) atomicOr(&acc.ovf[t], 1u);
-      pl = l2;
-      ph = h2;
-    }
-    if (acc.per_src) atomic_add128(&acc.per_src[2 * (u * T + t)], pl, ph);
-    if (T == 1) {
-      uint64_t s = lo0 + pl;
-      hi0 += ph + (s < pl ? 1u : 0u);
-      lo0 = s;
-    } else {
-      atomic_add128(&s_acc[2 * t], pl, ph);
+    for (int t = 0; t < T; t++) {
+      const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+      if (cu == cv) continue;
+      const uint64_t *ar = a.val + (e * T + t) * Ca;
+      const uint64_t *br = bb.val + (eb * T + t) * Cb;
+      uint64_t lo = 0, hi = 0;
+      bool of = false;
+      for (int c = 0; c < Ca; c++) {
+        const uint64_t x = ar[c];
+        if (!x) continue;
+        const uint32_t R1 = spread2(s_ua[c], cu, cv);
+        const uint32_t R2 = Kmask & ~R1 & ~(1u << cu) & ~(1u << cv);
+        const uint64_t y = br[s_rank[squeeze2(R2, cu, cv)]];
+        if (!y) continue;
+        uint64_t pl = x * y, ph = __umul64hi(x, y);
+        if (w != 1) {
+          const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
+          const uint64_t h2 = ph * w + c2;
+          if (__umul64hi(ph, w) != 0 || h2 < c2) of = true;
+          pl = l2;
+          ph = h2;
+        }
+        const uint64_t sl = lo + pl;
+        hi += ph + (sl < pl ? 1u : 0u);
+        lo = sl;
+      }
+      if (of) atomicOr(&acc.ovf[t], 1u);
+      if (!(lo | hi)) continue;
+      if (acc.per_src) atomic_add128(&acc.per_src[2 * (u * T + t)], lo, hi);
+      atomic_add128(&s_acc[2 * t], lo, hi);
     }
   }
-  if (T == 1 && (lo0 | hi0)) atomic_add128(&s_acc[0], lo0, hi0);
   __syncthreads();
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (s_acc[2 * t] | s_acc[2 * t + 1]) atomic_add128(&acc.sum[2 * t], s_acc[2 * t], s_acc[2 * t + 1]);
@@ -1190,6 +1227,19 @@ void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t
     hipLaunchKernelGGL(k_mask_or, dim3((unsigned)std::min<int64_t>((grp.n_lim + BLK - 1) / BLK, 8192)), dim3(BLK), 0,
                        st, a.mask, dst.mask, grp.n_lim, first);
 }
+void launch_axpyn(const GroupDev &grp, LevelDev L, const RegDev *a, const uint64_t *w, int nterms, RegDev dst,
+                  uint32_t *ovf, hipStream_t st) {
+  AxpyTerms tm{};
+  tm.n = nterms;
+  for (int q = 0; q < nterms; q++) {
+    tm.a[q] = a[q];
+    tm.w[q] = w[q];
+  }
+  hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, L, tm, dst, ovf);
+  if (grp.dense)
+    hipLaunchKernelGGL(k_mask_orn, dim3((unsigned)std::min<int64_t>((grp.n_lim + BLK - 1) / BLK, 8192)), dim3(BLK), 0,
+                       st, tm, dst.mask, grp.n_lim);
+}
 void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_v, dim3((unsigned)std::min<int64_t>((n + BLK - 1) / BLK, 8192)), dim3(BLK), 0, st, p, n,
@@ -1198,7 +1248,7 @@ void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
 
 void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,
                   uint64_t w, AccDev acc, hipStream_t st) {
-  hipLaunchKernelGGL(k_mroot, dim3(fgrid(grp, (int64_t)grp.T * a.C)), dim3(BLK), 0, st, grp, n, colr, La, Lb, a, b, w,
+  hipLaunchKernelGGL(k_mroot, dim3(fgrid(grp, 1)), dim3(BLK), 0, st, grp, n, colr, La, Lb, a, b, w,
                      acc, cur_lut());
 }
 
