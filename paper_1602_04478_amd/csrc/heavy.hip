@@ -866,6 +866,113 @@ __global__ void k_fill_v(uint64_t *p, int64_t n, uint64_t x) {
     p[i] = x;
 }
 
+// ------------------------------------------------------------------ dense groups: live rows only
+// A wavefront per vertex v walks the live rows (set bits of v's activity
+// word) times their slots; a vertex with no live row costs one load.
+__device__ __forceinline__ int nth_bit(uint64_t m, int k) {  // k < popcount(m)
+  int pos = 0;
+  for (int sh = 32; sh; sh >>= 1) {
+    const uint64_t lo = m & ((1ull << sh) - 1ull);
+    const int c = __popcll(lo);
+    if (k >= c) {
+      k -= c;
+      m >>= sh;
+      pos += sh;
+    } else {
+      m = lo;
+    }
+  }
+  return pos;
+}
+
+__global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const uint8_t *colr, RegDev a, RegDev dst,
+                                                  TabDev nt, uint32_t *ovf, const uint16_t *lut) {
+  __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_uo[256];
+  load_rank(s_rank, lut);
+  const int T = grp.T, C = dst.C, Ca = a.C, B = grp.B;
+  for (int c = threadIdx.x; c < C; c += BLK) s_uo[c] = unrank(lut, dst.s - 2, c);
+  __syncthreads();
+  const int rA = nt.s - 1;
+  const int per = T * C;
+  const int lane = threadIdx.x % 64;
+  const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
+  uint64_t ofm = 0;
+  for (int64_t v = wave; v < grp.n_lim; v += nwave) {
+    const uint64_t m = a.mask[v];
+    if (!m) continue;
+    const int items = __popcll(m) * per;
+    for (int it = lane; it < items; it += 64) {
+      const int q = it / per, r = it - q * per, t = r / C, c = r - t * C;
+      const int b = nth_bit(m, q);
+      const int64_t e = v * B + b;
+      const int64_t u = grp.src[b];
+      uint64_t acc = 0;
+      bool of = false;
+      if (v < u) {
+        const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+        if (cu != cv) {
+          const uint32_t Rp = spread2(s_uo[c], cu, cv);
+          const uint64_t *ar = a.val + (e * T + t) * Ca;
+          const uint64_t *nr = nt.val + (v * T + t) * nt.C;
+          uint32_t sA = Rp;
+          for (;;) {
+            if (__popc(sA) == rA) {
+              const uint64_t y = nr[s_rank[squeeze1(sA, cv)]];
+              if (y) {
+                const uint64_t x = ar[s_rank[squeeze2(Rp & ~sA, cu, cv)]];
+                if (x) add_ck(acc, mul_ck(x, y, of), of);
+              }
+            }
+            if (sA == 0) break;
+            sA = (sA - 1) & Rp;
+          }
+        }
+      }
+      dst.val[e * per + r] = acc;
+      if (of) ofm |= 1ull << t;
+    }
+  }
+  flag_trials(ovf, ofm);
+}
+
+__global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, AxpyTerms tm, RegDev dst, uint32_t *ovf) {
+  const int T = grp.T, C = dst.C, B = grp.B;
+  const int per = T * C;
+  const int lane = threadIdx.x % 64;
+  const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
+  uint64_t ofm = 0;
+  for (int64_t v = wave; v < grp.n_lim; v += nwave) {
+    uint64_t mt[4] = {0, 0, 0, 0};
+    uint64_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+      if (q < tm.n) {
+        mt[q] = tm.a[q].mask[v];
+        m |= mt[q];
+      }
+    if (lane == 0) dst.mask[v] = m;
+    if (!m) continue;
+    const int items = __popcll(m) * per;
+    for (int it = lane; it < items; it += 64) {
+      const int q0 = it / per, r = it - q0 * per;
+      const int b = nth_bit(m, q0);
+      const int64_t i = (v * B + b) * per + r;
+      bool of = false;
+      uint64_t y = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if (q >= tm.n || !((mt[q] >> b) & 1ull)) continue;
+        const uint64_t x = tm.a[q].val[i];
+        if (x) add_ck(y, mul_ck(tm.w[q], x, of), of);
+      }
+      dst.val[i] = y;
+      if (of) ofm |= 1ull << (r / C);
+    }
+  }
+  flag_trials(ovf, ofm);
+}
+
 // ------------------------------------------------------------------ root merge
 // count[t] += w * sum over entries (v, b) of both levels of
 //             sum over R of a[(v,b)][R] * b[(v,b)][K \ {chi u, chi v} \ R]
@@ -1215,6 +1322,11 @@ void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
 
 void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev L, RegDev a, RegDev dst,
                TabDev ntab, uint32_t *ovf, hipStream_t st) {
+  if (grp.dense) {
+    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
+    hipLaunchKernelGGL(k_nj_dense, dim3(gr), dim3(BLK), 0, st, grp, g.n, colr, a, dst, ntab, ovf, cur_lut());
+    return;
+  }
   hipLaunchKernelGGL(k_nj, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, g.n, colr, L, a, dst,
                      ntab, ovf, cur_lut());
 }
@@ -1235,10 +1347,12 @@ void launch_axpyn(const GroupDev &grp, LevelDev L, const RegDev *a, const uint64
     tm.a[q] = a[q];
     tm.w[q] = w[q];
   }
+  if (grp.dense) {  // the activity word of dst is written by the same pass
+    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
+    hipLaunchKernelGGL(k_axpyn_dense, dim3(gr), dim3(BLK), 0, st, grp, tm, dst, ovf);
+    return;
+  }
   hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, L, tm, dst, ovf);
-  if (grp.dense)
-    hipLaunchKernelGGL(k_mask_orn, dim3((unsigned)std::min<int64_t>((grp.n_lim + BLK - 1) / BLK, 8192)), dim3(BLK), 0,
-                       st, tm, dst.mask, grp.n_lim);
 }
 void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
   if (n <= 0) return;
