@@ -226,7 +226,8 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
 // dst[(w,b)][R'] = sum over v in N(w), v < u_b, (v,b) an entry of the lower
 // level, of sum over splits R' \ {chi v} = R + Re of a[(v,b)][R] * E(v,w)[Re].
 constexpr int WAVE = 64;
-constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
+constexpr int VMAX_C = 96;
+constexpr int EJ_BLK = 256;  // four wavefronts per workgroup share the rank tables (narrow rows)  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
 
 // One wavefront per output entry (w, b); per trial, w's neighbours below u_b
 // are taken 64 at a time in two phases:
@@ -431,39 +432,40 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {  // k < popcount
 
 // dynamic LDS of k_ejv: lane-owned columns, then (with an epilogue) the
 // operands' rows, the unrank lists and the root-merge sums
-__host__ __device__ constexpr size_t ejv_lds(int ncols, int nregs, bool epi) {
-  return (size_t)ncols * WAVE * 8 + (epi ? (size_t)nregs * WAVE * 8 + (LUT_SIZE - LUT_UNRANK) * 2 + 2 * WAVE * 8 : 0);
+__host__ __device__ constexpr size_t ejv_lds(int ncols, int nregs, bool epi, int nb) {
+  return (size_t)ncols * nb * 8 + (epi ? (size_t)nregs * nb * 8 + (LUT_SIZE - LUT_UNRANK) * 2 + 2 * WAVE * 8 : 0);
 }
+constexpr size_t EJV_LDS_MAX = 56 * 1024;
 
-template <bool ANN, int SW, bool EPI>
-__global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
+template <bool ANN, int SW, bool EPI, int NB>
+__global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                                               const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
                                               AccDev accd, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
   __shared__ int32_t s_src[WAVE];
-  __shared__ uint64_t s_live[EPI_MAX_REGS * (WAVE / SW)];  // dense: per written register and group, live rows
+  __shared__ uint64_t s_live[EPI_MAX_REGS * (NB / SW)];  // dense: per written register and group, live rows
   extern __shared__ uint64_t accs[];  // [columns][64]: lane-owned columns, EdgeJoin output first
-  int64_t *const s_rid = (int64_t *)(accs + (size_t)epi.ncols * WAVE);  // [regs][64] operands' rows
-  uint16_t *const s_unr = (uint16_t *)(s_rid + (size_t)epi.nregs * WAVE);  // unrank lists and offsets
+  int64_t *const s_rid = (int64_t *)(accs + (size_t)epi.ncols * NB);  // [regs][64] operands' rows
+  uint16_t *const s_unr = (uint16_t *)(s_rid + (size_t)epi.nregs * NB);  // unrank lists and offsets
   uint64_t *const s_msum = (uint64_t *)(s_unr + (LUT_SIZE - LUT_UNRANK));  // [64] x (lo, hi)
   load_rank(s_rank, lut);
+  const int tid = threadIdx.x;
   if (EPI) {
-    s_msum[threadIdx.x] = 0;
-    s_msum[threadIdx.x + WAVE] = 0;
-    for (int i = threadIdx.x; i < LUT_SIZE - LUT_UNRANK; i += WAVE) s_unr[i] = lut[LUT_UNRANK + i];
+    if (tid < 2 * WAVE) s_msum[tid] = 0;
+    for (int i = tid; i < LUT_SIZE - LUT_UNRANK; i += NB) s_unr[i] = lut[LUT_UNRANK + i];
   }
   // unranked slot idx of rank r from the LDS copy (layout of the global table, shifted)
   auto unr = [&](int r, int idx) -> uint32_t { return s_unr[s_unr[LUT_OFF - LUT_UNRANK + r] + idx]; };
   const LevelDev Lout = epi.regs[0].L;
   const RegDev dst = epi.regs[0].r;
-  uint64_t *const acc = accs + (size_t)epi.regs[0].col * WAVE;
+  uint64_t *const acc = accs + (size_t)epi.regs[0].col * NB;
   const int T = grp.T, B = grp.B, C = dst.C, Ca = a.C;
   const int ra = a.s - 2, ro = dst.s - 2;
   const int W = ANN ? C : Ca;
-  const int lane = threadIdx.x;
-  for (int c = lane; c < W; c += WAVE) s_um[c] = unrank(lut, ANN ? ro : ra, c);
-  s_src[lane] = lane < B ? grp.src[lane] : -1;
+  const int lane = tid % WAVE;
+  for (int c = tid; c < W; c += NB) s_um[c] = unrank(lut, ANN ? ro : ra, c);
+  if (tid < WAVE) s_src[tid] = tid < B ? grp.src[tid] : -1;
   __syncthreads();
   constexpr int NG = WAVE / SW;  // groups per wavefront
   const int gl = lane % SW, gbase = lane - gl;
@@ -475,7 +477,9 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
   const uint32_t Kmask = (1u << grp.k) - 1u;
   uint64_t ofm = 0, n_scan = 0, n_rows = 0, n_ent = 0;
   uint64_t mlo = 0, mhi = 0;  // this lane's root-merge sum (its trial)
-  for (int64_t w = (int64_t)blockIdx.x * NG + lane / SW; w < grp.n_lim; w += (int64_t)gridDim.x * NG) {
+  constexpr int WPB = NB / WAVE;  // wavefronts per workgroup
+  for (int64_t w = ((int64_t)blockIdx.x * WPB + tid / WAVE) * NG + lane / SW; w < grp.n_lim;
+       w += (int64_t)gridDim.x * WPB * NG) {
     // output rows at w: dense -- every source above w; sparse -- the marks
     uint64_t ob = 0;
     if (grp.dense) {
@@ -491,7 +495,7 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
     }
     const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
     if (grp.dense && gl == 0)
-      for (int j = 0; j < epi.nregs; j++) s_live[j * NG + lane / SW] = 0;
+      for (int j = 0; j < epi.nregs; j++) s_live[j * (NB / SW) + tid / SW] = 0;
     uint64_t rest = ob;
     while (rest) {
       // this pass: the first Bc sources of rest
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
         cw = colr[(int64_t)lt * n + w];
         act = cu != cw;
       }
-      for (int o = 0; o < epi.ncols; o++) accs[o * WAVE + lane] = 0;
+      for (int o = 0; o < epi.ncols; o++) accs[o * NB + tid] = 0;
       bool of = false;
       for (int64_t j0 = r0; j0 < r1; j0 += SW) {
         const int64_t ee = j0 + gl;
@@ -535,7 +539,37 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
         const bool stop = gballot(vj == INT64_MAX) != 0;
         // one trial: the neighbour's colour travels with it (loaded by its own lane)
         const int cvj = (T == 1 && inb) ? colr[vj] : 0;
-        if (!ANN) {
+        if (!ANN && SW < 64) {
+          // quarter wavefronts: one neighbour per step, few registers (more
+          // wavefronts in flight hide the per-vertex load chains)
+          while (todo) {
+            const int jA = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int64_t vA = __shfl(vj, jA, SW);
+            const uint64_t ibA = __shfl(inb, jA, SW);
+            const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA, SW);
+            const int64_t bA = grp.dense ? 0 : __shfl(bj, jA, SW);
+            int cA = __shfl(cvj, jA, SW);
+            bool okA = act && vA < u && ((ibA >> b) & 1ull);
+            if (T > 1 && okA) cA = colr[(int64_t)lt * n + vA];
+            okA = okA && cA != cu && cA != cw;
+            if (!okA) continue;
+            n_rows++;
+            const uint64_t *rowA =
+                a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & ((1ull << b) - 1ull))) * T + lt) * Ca;
+            for (int c0 = 0; c0 < Ca; c0 += 4) {
+              uint64_t xa[4];
+#pragma unroll
+              for (int q = 0; q < 4; q++) xa[q] = c0 + q < Ca ? rowA[c0 + q] : 0;
+#pragma unroll
+              for (int q = 0; q < 4; q++) {
+                if (!xa[q]) continue;
+                const uint32_t R = spread2(s_um[c0 + q], cu, cA);
+                if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * NB + tid], xa[q], of);
+              }
+            }
+          }
+        } else if (!ANN) {
           // two neighbours per step, both rows' loads in flight together
           while (todo) {
             const int jA = __builtin_ctzll(todo);
@@ -573,11 +607,11 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
               for (int q = 0; q < 8; q++) {
                 if (xa[q]) {
                   const uint32_t R = spread2(s_um[c0 + q], cu, cA);
-                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * WAVE + lane], xa[q], of);
+                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * NB + tid], xa[q], of);
                 }
                 if (xb[q]) {
                   const uint32_t R = spread2(s_um[c0 + q], cu, cB);
-                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cB), cu, cw)] * WAVE + lane], xb[q], of);
+                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cB), cu, cw)] * NB + tid], xb[q], of);
                 }
               }
             }
@@ -617,7 +651,7 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
                 if (s1 == 0) break;
                 s1 = (s1 - 1) & R;
               }
-              if (sum) add_ck(acc[co * WAVE + lane], sum, of);
+              if (sum) add_ck(acc[co * NB + tid], sum, of);
             }
           }
         }
@@ -633,12 +667,12 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
             if (grp.dense) id = ((R.r.mask[w] >> b) & 1ull) ? w * B + b : -1;
             else id = sparse_entry(R.L, w, b);
           }
-          s_rid[j * WAVE + lane] = id;
+          s_rid[j * NB + tid] = id;
         }
         auto val = [&](int j, int slot) -> uint64_t {
           const EpiReg &R = epi.regs[j];
-          if (R.col >= 0) return accs[(R.col + slot) * WAVE + lane];
-          const int64_t id = s_rid[j * WAVE + lane];
+          if (R.col >= 0) return accs[(R.col + slot) * NB + tid];
+          const int64_t id = s_rid[j * NB + tid];
           return id < 0 ? 0 : R.r.val[(id * T + lt) * R.r.C + slot];
         };
         for (int oi = 0; oi < epi.nops; oi++) {
@@ -665,15 +699,15 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
                   sA = (sA - 1) & Rp;
                 }
               }
-              accs[(D.col + c) * WAVE + lane] = v;
+              accs[(D.col + c) * NB + tid] = v;
             }
           } else if (op.kind == EPI_AXPY) {
             const EpiReg &D = epi.regs[op.dst];
             for (int c = 0; c < D.r.C; c++) {
-              uint64_t y = op.first ? 0 : accs[(D.col + c) * WAVE + lane];
+              uint64_t y = op.first ? 0 : accs[(D.col + c) * NB + tid];
               const uint64_t x = val(op.a, c);
               if (x) add_ck(y, mul_ck(op.w, x, of), of);
-              accs[(D.col + c) * WAVE + lane] = y;
+              accs[(D.col + c) * NB + tid] = y;
             }
           } else if (cu != cw) {  // EPI_MROOT: the cycle closes at w
             const EpiReg &A = epi.regs[op.a];
@@ -711,23 +745,23 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
         uint64_t mine = 0;
         if (grp.dense && b >= 0) {
           bool nz = false;
-          for (int o = 0; o < Cj; o++) nz |= accs[(R.col + o) * WAVE + lane] != 0;
+          for (int o = 0; o < Cj; o++) nz |= accs[(R.col + o) * NB + tid] != 0;
           mine = nz ? 1ull << b : 0;
         }
         if (grp.dense)
           for (int o = SW / 2; o > 0; o >>= 1) mine |= (uint64_t)__shfl_xor(mine, o, SW);
-        if (grp.dense && gl == 0) s_live[j * NG + lane / SW] |= mine;
+        if (grp.dense && gl == 0) s_live[j * (NB / SW) + tid / SW] |= mine;
         if (b >= 0 && (!grp.dense || ((mine >> b) & 1ull))) {
           const int64_t id = grp.dense ? w * B + b : sparse_entry(R.L, w, b);
           uint64_t *drow = R.r.val + (id * T + lt) * Cj;
-          for (int o = 0; o < Cj; o++) drow[o] = accs[(R.col + o) * WAVE + lane];
+          for (int o = 0; o < Cj; o++) drow[o] = accs[(R.col + o) * NB + tid];
         }
       }
     }
     if (gl == 0) {
       if (grp.dense)
         for (int j = 0; j < epi.nregs; j++)
-          if (epi.regs[j].write) epi.regs[j].r.mask[w] = s_live[j * NG + lane / SW];
+          if (epi.regs[j].write) epi.regs[j].r.mask[w] = s_live[j * (NB / SW) + tid / SW];
       n_ent += __popcll(ob);
     }
   }
@@ -735,8 +769,8 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
   if (EPI) {
     if (mlo | mhi) atomic_add128(&s_msum[2 * lt], mlo, mhi);
     __syncthreads();
-    if (lane < T && (s_msum[2 * lane] | s_msum[2 * lane + 1]))
-      atomic_add128(&accd.sum[2 * lane], s_msum[2 * lane], s_msum[2 * lane + 1]);
+    if (tid < T && (s_msum[2 * tid] | s_msum[2 * tid + 1]))
+      atomic_add128(&accd.sum[2 * tid], s_msum[2 * tid], s_msum[2 * tid + 1]);
   }
   if (grp.prof) {
     for (int o = 32; o > 0; o >>= 1) {
@@ -745,7 +779,7 @@ __global__ __launch_bounds__(WAVE) void k_ejv(GraphDev g, GroupDev grp, const ui
       n_ent += __shfl_xor(n_ent, o);
     }
     if (lane == 0) {
-      uint64_t *pc = grp.prof + 3 * (blockIdx.x % PROF_LANES);  // spread over lanes: no hot address
+      uint64_t *pc = grp.prof + 3 * ((blockIdx.x * WPB + tid / WAVE) % PROF_LANES);  // spread over lanes: no hot address
       atomicAdd((unsigned long long *)&pc[0], (unsigned long long)n_scan);
       atomicAdd((unsigned long long *)&pc[1], (unsigned long long)n_rows);
       atomicAdd((unsigned long long *)&pc[2], (unsigned long long)n_ent);
@@ -1270,31 +1304,37 @@ void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, 
 }
 
 bool epi_fits(int ncols, int T, int etab_C) {
-  return ncols <= VMAX_C && T <= WAVE && etab_C <= 256 && ejv_lds(ncols, EPI_MAX_REGS, true) <= 56 * 1024;
+  return ncols <= VMAX_C && T <= WAVE && etab_C <= 256 && ejv_lds(ncols, EPI_MAX_REGS, true, WAVE) <= EJV_LDS_MAX;
 }
 
 void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                    const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st) {
   const bool ep = epi.nops > 0;
-  const size_t lds = ejv_lds(epi.ncols, epi.nregs, ep);
+  // four wavefronts per workgroup when their LDS columns fit, else one
+  const bool wide = ejv_lds(epi.ncols, epi.nregs, ep, EJ_BLK) <= EJV_LDS_MAX;
+  const int nb = wide ? EJ_BLK : WAVE;
+  const size_t lds = ejv_lds(epi.ncols, epi.nregs, ep, nb);
   // sparse groups meet few sources per vertex: four vertices per wavefront
   const bool quarter = !grp.dense && grp.T <= 16;
-  const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;
-  const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(nw, 32768));
-#define CC_EJV(ANN_, SW_, EPI_)                                                                             \
-  hipLaunchKernelGGL((k_ejv<ANN_, SW_, EPI_>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, a, epi, etab, \
+  const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;  // wavefronts' worth of vertices
+  const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((nw + nb / WAVE - 1) / (nb / WAVE), 32768 / (nb / WAVE)));
+#define CC_EJV(ANN_, SW_, EPI_, NB_)                                                                          \
+  hipLaunchKernelGGL((k_ejv<ANN_, SW_, EPI_, NB_>), dim3(gr), dim3(NB_), lds, st, g, grp, colr, Lin, a, epi, etab, \
                      e_src_first, ovf, acc, cur_lut())
+#define CC_EJV2(ANN_, SW_, EPI_) \
+  if (wide) CC_EJV(ANN_, SW_, EPI_, EJ_BLK); else CC_EJV(ANN_, SW_, EPI_, WAVE)
   const int sel = (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
   switch (sel) {
-    case 0: CC_EJV(false, 64, false); break;
-    case 1: CC_EJV(false, 64, true); break;
-    case 2: CC_EJV(false, 16, false); break;
-    case 3: CC_EJV(false, 16, true); break;
-    case 4: CC_EJV(true, 64, false); break;
-    case 5: CC_EJV(true, 64, true); break;
-    case 6: CC_EJV(true, 16, false); break;
-    default: CC_EJV(true, 16, true); break;
+    case 0: CC_EJV2(false, 64, false); break;
+    case 1: CC_EJV2(false, 64, true); break;
+    case 2: CC_EJV2(false, 16, false); break;
+    case 3: CC_EJV2(false, 16, true); break;
+    case 4: CC_EJV2(true, 64, false); break;
+    case 5: CC_EJV2(true, 64, true); break;
+    case 6: CC_EJV2(true, 16, false); break;
+    default: CC_EJV2(true, 16, true); break;
   }
+#undef CC_EJV2
 #undef CC_EJV
 }
 
