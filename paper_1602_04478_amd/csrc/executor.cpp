@@ -202,15 +202,18 @@ struct Bytes {
 };
 Bytes solver_bytes(const DevGraph &g, const Plan &p, int T) {
   const uint64_t n = (uint64_t)std::max<int64_t>(1, g.n);
-  uint64_t slots = 0, nregs = 0;
+  // registers are pooled by index across the programs: register r holds the
+  // widest row any program puts there
+  std::vector<uint64_t> rmax;
   int dmax = 1;
   for (auto &P : p.programs) {
-    uint64_t sl = 0;
-    for (int s : P.reg_s) sl += slots_pair(p.k, s);
-    slots = std::max(slots, sl);
-    nregs = std::max<uint64_t>(nregs, P.reg_s.size());
+    if (rmax.size() < P.reg_s.size()) rmax.resize(P.reg_s.size(), 0);
+    for (size_t r = 0; r < P.reg_s.size(); r++) rmax[r] = std::max<uint64_t>(rmax[r], slots_pair(p.k, P.reg_s[r]));
     dmax = std::max(dmax, P.max_depth);
   }
+  uint64_t slots = 0;
+  for (auto c : rmax) slots += c;
+  const uint64_t nregs = rmax.size();
   Bytes b;
   b.fixed = table_bytes(g, p, T) + 2 * n * T                   // tables, colours (+ host-colour staging)
             + nregs * 8 * n                                    // activity masks
