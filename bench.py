@@ -67,7 +67,8 @@ def query_of(name):
 KERNEL_OF = {  # profiled op name -> the HIP kernel that runs it
     "edgejoin": "k_ej", "nodejoin": "k_nj", "axpy": "k_axpy", "merge_root": "k_mroot", "init": "k_init",
     "merge_u": "k_munary", "merge_v": "k_munary", "merge_edge": "k_medge", "merge_edge_t": "k_medge_t",
-    "level_build_sparse": "level build", "light": "k_light", "leaf": "k_leaf", "root_single": "k_root_single",
+    "level_build_sparse": "level build", "light": "k_light", "light_large": "k_light", "leaf": "k_leaf",
+    "root_single": "k_root_single",
 }
 
 

@@ -189,6 +189,10 @@ int64_t light_scratch_bytes(const DevGraph &g, int T) {
   if (const char *ev = getenv("CC_LIGHT_SCRATCH")) return std::max<int64_t>(4096, atoll(ev));
   return std::max<int64_t>(64 << 10, std::min<int64_t>(b, 2 << 20));
 }
+bool large_light_on() {
+  const char *ev = getenv("CC_LIGHT_LARGE");
+  return ev && *ev == '1';
+}
 int light_grid(int device) {
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) ncu = 256;
@@ -218,7 +222,8 @@ Bytes solver_bytes(const DevGraph &g, const Plan &p, int T) {
   b.fixed = table_bytes(g, p, T) + 2 * n * T                   // tables, colours (+ host-colour staging)
             + nregs * 8 * n                                    // activity masks
             + (uint64_t)dmax * (12 * n + 4 * (n / 4096 + 2))   // level marks and bases
-            + (uint64_t)light_scratch_bytes(g, T) * light_grid(g.device) + (64 << 20);
+            + (uint64_t)light_scratch_bytes(g, T) * light_grid(g.device) + (64 << 20)
+            + (large_light_on() ? (uint64_t)(32 << 20) * (light_grid(g.device) / 3) : 0);  // large light stage
   b.per_B = 8 * n * T * slots + (uint64_t)dmax * 8 * n;        // registers, level lists
   return b;
 }
@@ -630,14 +635,16 @@ class Solver {
     int64_t B;
     bool dense;
   };
-  struct Light {  // one cycle block's one-workgroup tier
+  struct Light {  // one stage of a cycle block's one-workgroup tier
     bool probed = false;
+    bool large = false;          // the big-LDS kernel (takes what the small one hands back)
     std::vector<int32_t> src;    // sources it runs
-    std::vector<int32_t> fails;  // sources it hands back (descending), run as groups
+    std::vector<int32_t> fails;  // sources it hands back (descending)
     DevMem d_ops, d_rd, d_rC, d_rs, d_tv, d_ctr, d_fail, d_src, d_fails;
     LightArgs la{};
     int grid = 0;
   };
+  void run_light(Light &L, bool probe, int Tg, Profiler *prof);
   void enqueue(int Tg, bool seed_dev, bool probe, Profiler *prof);
   void enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof);
   void run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof);
@@ -676,8 +683,11 @@ class Solver {
   std::vector<DevMem> tabs_;
   std::vector<RegBuf> regs_;
   std::vector<LevelBuf> levels_;
-  std::vector<Light> light_;
-  DevMem light_scratch_buf_;
+  std::vector<Light> light_;   // small stage per block
+  std::vector<Light> light2_;  // large stage per block (used when use_large_)
+  bool use_large_ = false;
+  int64_t light_scratch_large_ = 32 << 20;
+  DevMem light_scratch_buf_, light_scratch_large_buf_;
   AccDev acc_{};
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
@@ -844,6 +854,43 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
       light_scratch_buf_.alloc((size_t)light_scratch_ * L.grid);
   }
   for (auto &L : light_) L.la.scratch = light_scratch_buf_.as<uint8_t>();
+  // the large stage (CC_LIGHT_LARGE=1): one workgroup per compute unit.  Off by
+  // default: on the 1e6-vertex workload it takes 9.7k of the 23k hand-backs
+  // in 0.26 s but saves the grouped path only about as much.
+  use_large_ = large_light_on();
+  if (const char *ev = getenv("CC_LIGHT_SCRATCH_LARGE")) light_scratch_large_ = std::max<int64_t>(4096, atoll(ev));
+  light2_.resize(p.blocks.size());
+  if (use_large_) {
+    const int lgrid2 = lgrid / 3;
+    bool any = false;
+    for (size_t bi = 0; bi < p.blocks.size(); bi++) {
+      Light &L = light_[bi], &L2 = light2_[bi];
+      L2.probed = true;
+      if (L.src.empty()) continue;
+      const size_t ns = L.src.size();
+      L2.probed = false;
+      L2.large = true;
+      L2.grid = std::max(1, lgrid2);
+      L2.d_ctr.alloc(sizeof(uint64_t));
+      L2.d_fail.alloc(4 * ns);
+      L2.d_src.alloc(4 * ns);
+      L2.d_fails.alloc(4 * ns);
+      L2.la = L.la;  // same program, tables and outputs
+      L2.la.src = L2.d_src.as<int32_t>();
+      L2.la.nsrc = 0;
+      L2.la.next = L2.d_ctr.as<uint32_t>();
+      L2.la.fail = L2.d_fail.as<int32_t>();
+      L2.la.nfail = L2.d_ctr.as<uint32_t>() + 1;
+      L2.la.scratch_per_wg = light_scratch_large_;
+      any = true;
+    }
+    if (any) {
+      light_scratch_large_buf_.alloc((size_t)light_scratch_large_ * std::max(1, lgrid / 3));
+      for (auto &L2 : light2_) L2.la.scratch = light_scratch_large_buf_.as<uint8_t>();
+    }
+  } else {
+    for (auto &L2 : light2_) L2.probed = true;
+  }
   (void)lut_device(g.device);  // built before any capture
   HIP_CHECK(hipStreamSynchronize(st));
 }
@@ -1101,51 +1148,66 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
               out, C_out, prof);
     if (progress) fprintf(stderr, "[cc] block %zu: dense group at source %lld enqueued\n", bi, (long long)i), fflush(stderr);
   }
-  // 2. one workgroup per source for the rest
-  Light &L = light_[bi];
-  if (!L.src.empty()) {
-    L.la.T = Tg;
-    L.la.acc = acc_;
-    launch_fill_u64((uint64_t *)L.d_ctr.p, 1, st);
-    if (prof) prof->begin("light", false, 0, 0, 0);
-    launch_light(L.la, L.grid, st);
-    HIP_CHECK(hipGetLastError());
-    if (prof) prof->end();
-    if (probe && !L.probed) {
-      // learn what it hands back: from now on those sources run as groups
-      uint32_t hc[2];
-      HIP_CHECK(hipMemcpyAsync(hc, L.d_ctr.p, 8, hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipStreamSynchronize(st));
-      std::vector<int32_t> f(hc[1]);
-      if (hc[1]) HIP_CHECK(hipMemcpy(f.data(), L.d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost));
-      std::sort(f.begin(), f.end(), std::greater<int32_t>());
-      std::vector<int32_t> keep;
-      {
-        std::vector<int32_t> fs = f;
-        std::sort(fs.begin(), fs.end());
-        for (int32_t s : L.src)
-          if (!std::binary_search(fs.begin(), fs.end(), s)) keep.push_back(s);
-      }
-      L.src = keep;
-      L.fails = f;
-      L.la.nsrc = (int)keep.size();
-      if (!keep.empty())
-        HIP_CHECK(hipMemcpyAsync(L.d_src.p, keep.data(), 4 * keep.size(), hipMemcpyHostToDevice, st));
-      if (!f.empty()) HIP_CHECK(hipMemcpyAsync(L.d_fails.p, f.data(), 4 * f.size(), hipMemcpyHostToDevice, st));
-      L.probed = true;
+  // 2. one workgroup per source for the rest: the small stage, then the
+  // large stage on what the small one hands back
+  Light &L = light_[bi], &L2 = light2_[bi];
+  run_light(L, probe, Tg, prof);
+  const bool two = use_large_ && L2.large;
+  if (two) {
+    if (probe && !L2.probed && L2.src.empty() && L.probed && !L.fails.empty()) {
+      L2.src = L.fails;
+      L2.la.nsrc = (int)L2.src.size();
+      HIP_CHECK(hipMemcpyAsync(L2.d_src.p, L2.src.data(), 4 * L2.src.size(), hipMemcpyHostToDevice, st));
     }
+    run_light(L2, probe, Tg, prof);
+    if (L.probed && L.fails.empty()) L2.probed = true;
   }
+  Light &LF = two ? L2 : L;  // whose hand-backs run as groups
   // 3. grouped path for what the one-workgroup tier does not take
-  if (!L.fails.empty()) {
-    for (int64_t i = 0; i < (int64_t)L.fails.size(); i += z_.B_sparse) {
+  if (!LF.fails.empty()) {
+    for (int64_t i = 0; i < (int64_t)LF.fails.size(); i += z_.B_sparse) {
       run_group(P,
-                {L.d_fails.as<int32_t>() + i, L.fails.data() + i,
-                 std::min<int64_t>(z_.B_sparse, (int64_t)L.fails.size() - i), fallback_dense_},
+                {LF.d_fails.as<int32_t>() + i, LF.fails.data() + i,
+                 std::min<int64_t>(z_.B_sparse, (int64_t)LF.fails.size() - i), fallback_dense_},
                 Tg, out, C_out, prof);
       if (progress && (i / z_.B_sparse) % 32 == 0)
         fprintf(stderr, "[cc] block %zu: sparse group at source %lld of %zu enqueued\n", bi, (long long)i,
-                L.fails.size()), fflush(stderr);
+                LF.fails.size()), fflush(stderr);
     }
+  }
+}
+
+void Solver::run_light(Light &L, bool probe, int Tg, Profiler *prof) {
+  hipStream_t st = st_;
+  if (L.src.empty()) return;
+  L.la.T = Tg;
+  L.la.acc = acc_;
+  launch_fill_u64((uint64_t *)L.d_ctr.p, 1, st);
+  if (prof) prof->begin(L.large ? "light_large" : "light", false, 0, 0, 0);
+  launch_light(L.la, L.grid, L.large, st);
+  HIP_CHECK(hipGetLastError());
+  if (prof) prof->end();
+  if (probe && !L.probed) {
+    // learn what it hands back: from now on those sources go to the next stage
+    uint32_t hc[2];
+    HIP_CHECK(hipMemcpyAsync(hc, L.d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<int32_t> f(hc[1]);
+    if (hc[1]) HIP_CHECK(hipMemcpy(f.data(), L.d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost));
+    std::sort(f.begin(), f.end(), std::greater<int32_t>());
+    std::vector<int32_t> keep;
+    {
+      std::vector<int32_t> fs = f;
+      std::sort(fs.begin(), fs.end());
+      for (int32_t s2 : L.src)
+        if (!std::binary_search(fs.begin(), fs.end(), s2)) keep.push_back(s2);
+    }
+    L.src = keep;
+    L.fails = f;
+    L.la.nsrc = (int)keep.size();
+    if (!keep.empty()) HIP_CHECK(hipMemcpyAsync(L.d_src.p, keep.data(), 4 * keep.size(), hipMemcpyHostToDevice, st));
+    if (!f.empty()) HIP_CHECK(hipMemcpyAsync(L.d_fails.p, f.data(), 4 * f.size(), hipMemcpyHostToDevice, st));
+    L.probed = true;
   }
 }
 
@@ -1167,10 +1229,11 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
   }
   acc_.per_src = per_source ? d_per_.as<uint64_t>() : nullptr;
   bool probed = true;
-  std::vector<char> was_probed(light_.size());
+  std::vector<char> was_probed(2 * light_.size());
   for (size_t bi = 0; bi < light_.size(); bi++) {
-    was_probed[bi] = light_[bi].probed;
-    probed &= light_[bi].probed;
+    was_probed[2 * bi] = light_[bi].probed;
+    was_probed[2 * bi + 1] = light2_[bi].probed;
+    probed &= light_[bi].probed && light2_[bi].probed;
   }
   if (cs.from_seed) {
     uint64_t prm[2] = {cs.seed, (uint64_t)t0};
@@ -1211,9 +1274,12 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
   std::vector<uint32_t> ho(64);
   HIP_CHECK(hipMemcpyAsync(hs.data(), d_sum_.p, sizeof(uint64_t) * 2 * 64, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(ho.data(), d_ovf_.p, sizeof(uint32_t) * 64, hipMemcpyDeviceToHost, st));
-  std::vector<uint32_t> lf(2 * light_.size(), 0);
-  for (size_t bi = 0; bi < light_.size(); bi++)
-    if (!light_[bi].src.empty()) HIP_CHECK(hipMemcpyAsync(&lf[2 * bi], light_[bi].d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> lf(4 * light_.size(), 0);
+  for (size_t bi = 0; bi < light_.size(); bi++) {
+    if (!light_[bi].src.empty()) HIP_CHECK(hipMemcpyAsync(&lf[4 * bi], light_[bi].d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+    if (!light2_[bi].src.empty())
+      HIP_CHECK(hipMemcpyAsync(&lf[4 * bi + 2], light2_[bi].d_ctr.p, 8, hipMemcpyDeviceToHost, st));
+  }
   std::vector<uint64_t> hp;
   if (per_source) {
     hp.resize(2 * (size_t)g_.n * Tg);
@@ -1222,7 +1288,7 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
   HIP_CHECK(hipStreamSynchronize(st));
   prof.finish();
   for (size_t bi = 0; bi < light_.size(); bi++)
-    if (was_probed[bi] && lf[2 * bi + 1] != 0)
+    if ((was_probed[2 * bi] && lf[4 * bi + 1] != 0) || (was_probed[2 * bi + 1] && lf[4 * bi + 3] != 0))
       fail(CC_E_DEVICE, "the one-workgroup tier handed back a source it completed before");
   for (int t = 0; t < Tg; t++) {
     res.exact[t0 + t] = (u128)hs[2 * t] | ((u128)hs[2 * t + 1] << 64);

@@ -187,6 +187,7 @@ struct LightArgs {
 
 int light_max_depth();
 int light_max_regs();
-void launch_light(const LightArgs &a, int grid, hipStream_t st);
+// large: the variant with the big LDS key pool (one workgroup per compute unit)
+void launch_light(const LightArgs &a, int grid, bool large, hipStream_t st);
 
 }  // namespace cc

@@ -25,8 +25,12 @@ namespace {
 
 using namespace dev;
 
-constexpr int KPOOL = 6144;  // keys over all depths
-constexpr int EMAX = 4096;   // expansion buffer (with duplicates)
+// Two sizes: the small one (keys 6144, expansion buffer 4096) keeps several
+// workgroups per compute unit for the many small sources; the large one
+// (16384 / 16384, most of a compute unit's 160 KiB of LDS) takes what the
+// small one hands back.
+constexpr int KPOOL_S = 6144, EMAX_S = 4096;
+constexpr int KPOOL_L = 16384, EMAX_L = 16384;
 constexpr int DMAX = 12;
 constexpr int RMAX = 64;     // registers per program
 
@@ -89,10 +93,11 @@ __device__ void bitonic(int32_t *s, int n2) {
 
 __device__ __forceinline__ int64_t align8(int64_t x) { return (x + 7) & ~(int64_t)7; }
 
+template <int KPOOL, int EMAX>
 __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
   __shared__ uint16_t s_rank[2048];
-  __shared__ int32_t s_k[KPOOL];
-  __shared__ int32_t s_c[EMAX];
+  __shared__ int32_t s_k[KPOOL];   // keys over all depths
+  __shared__ int32_t s_c[EMAX];    // expansion buffer (with duplicates)
   __shared__ int s_koff[DMAX + 2];
   __shared__ int64_t s_mo[DMAX][3];  // per step: offsets of the match offsets, key positions, slots
   __shared__ int64_t s_roff[RMAX];
@@ -588,8 +593,11 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
 int light_max_depth() { return DMAX; }
 int light_max_regs() { return RMAX; }
 
-void launch_light(const LightArgs &a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_light, dim3(grid), dim3(BLK), 0, st, a);
+void launch_light(const LightArgs &a, int grid, bool large, hipStream_t st) {
+  if (large)
+    hipLaunchKernelGGL((k_light<KPOOL_L, EMAX_L>), dim3(grid), dim3(BLK), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_light<KPOOL_S, EMAX_S>), dim3(grid), dim3(BLK), 0, st, a);
 }
 
 }  // namespace cc

@@ -41,6 +41,7 @@ PATH_MODES = {
     "light": {"CC_DENSE": "none"},
     "light+fallback": {"CC_DENSE": "none", "CC_LIGHT_SCRATCH": "6000"},
     "light+densefallback": {"CC_LIGHT_SCRATCH": "6000", "CC_FALLBACK": "dense"},
+    "light-large": {"CC_DENSE": "none", "CC_LIGHT_SCRATCH": "6000", "CC_LIGHT_LARGE": "1"},
     "fused-dense": {"CC_DENSE": "all", "CC_FUSE": "1"},
     "fused-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_FUSE": "1"},
 }
