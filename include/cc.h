@@ -70,6 +70,7 @@ typedef struct {
   int32_t trial_group;     /* colourings processed together */
   int32_t light_max_keys;  /* per-level key capacity of the one-workgroup-per-source path */
   int32_t use_graphs;      /* 1: capture the launch sequence of a solve in a hipGraph and replay it */
+  int32_t dense_sources;   /* highest sources run as dense groups; -1: the library's cost-model cut */
 } cc_tuning;
 
 /* ------------------------------------------------------------------ graphs */

@@ -43,7 +43,8 @@ class KernelStat(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("group_sources", ctypes.c_int32), ("trial_group", ctypes.c_int32),
-                ("light_max_keys", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("light_max_keys", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("dense_sources", ctypes.c_int32)]
 
 
 _lib = None
@@ -239,7 +240,8 @@ def count_batch(g: Graph, queries, seeds, trials, tuning: dict | None = None, st
     est = np.zeros(nq, dtype=np.float64)
     tun = None
     if tuning:
-        tun = Tuning(**tuning)
+        tun = Tuning(**{"group_sources": 0, "trial_group": 0, "light_max_keys": 0, "use_graphs": 1,
+                        "dense_sources": -1, **tuning})
     _check(lib().cc_count_batch(g.h, nq, qs, _ptr(sd), _ptr(tr), _ptr(counts), _ptr(ovf), _ptr(est),
                                 ctypes.byref(tun) if tun else None, stream))
     return counts, ovf, est

@@ -65,6 +65,7 @@ cc::ExecOptions opts_from(const cc_tuning *t) {
     o.trial_group = t->trial_group;
     o.light_max_keys = t->light_max_keys;
     o.use_graphs = t->use_graphs;
+    o.dense_sources = t->dense_sources;
   }
   return o;
 }

@@ -132,6 +132,7 @@ struct ExecOptions {
   int trial_group = 0;
   int light_max_keys = 0;
   int use_graphs = 0;
+  int dense_sources = -1;         // sources run as dense groups (-1: the cost model's cut)
   uint64_t mem_budget = 0;        // bytes; 0 = from the device's free memory
 };
 

@@ -713,16 +713,24 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   // sources: lowcnt >= 2, descending rank
   for (int64_t r = g.n - 1; r >= 0; r--)
     if (g.h_lowcnt[r] >= 2) sources_.push_back((int32_t)r);
-  // dense cut: sources whose two-step reach covers a good part of their prefix
+  // dense cut.  A dense group scans every edge below its top source once per
+  // level (cost ~ rp[u], the directed edges of the vertices below u); a
+  // source in a sparse group costs about its two-step high-start reach r2(u).
+  // A source goes dense while 64 sources like it would cost the grouped
+  // sparse path more than one dense group: r2(u) * 64 * kappa >= rp[u], with
+  // kappa = 13 measured on the 1e6-vertex power-law workload (dense cuts of
+  // 0 .. 24576 sources: best near 3072).
   for (size_t i = 0; i < sources_.size(); i++) {
-    int64_t u = sources_[i];
-    if (g.h_r2[u] * 16 >= u && u > 4096) ndense_ = (int64_t)i + 1;
+    const int64_t u = sources_[i];
+    if (g.h_r2[u] * 64 * 13 >= g.h_rp[u] && u > 4096) ndense_ = (int64_t)i + 1;
     else break;
   }
+  if (opt.dense_sources >= 0) ndense_ = std::min<int64_t>(opt.dense_sources, (int64_t)sources_.size());
   // CC_DENSE=all / none overrides the choice (used to exercise both paths)
   if (const char *ev = getenv("CC_DENSE")) {
     if (!strcmp(ev, "all")) ndense_ = (int64_t)sources_.size();
-    if (!strcmp(ev, "none")) ndense_ = 0;
+    else if (!strcmp(ev, "none")) ndense_ = 0;
+    else if (*ev >= '0' && *ev <= '9') ndense_ = std::min<int64_t>(atoll(ev), (int64_t)sources_.size());
   }
   if (const char *ev = getenv("CC_LIGHT"))
     if (!strcmp(ev, "0")) use_light_ = false;
