@@ -227,6 +227,9 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
 // level, of sum over splits R' \ {chi v} = R + Re of a[(v,b)][R] * E(v,w)[Re].
 constexpr int WAVE = 64;
 constexpr int VMAX_C = 96;
+#ifndef EJ_UNROLL
+#define EJ_UNROLL 4  // slots of both rows loaded before they are added (two-neighbour steps)
+#endif
 constexpr int EJ_BLK = 256;  // four wavefronts per workgroup share the rank tables (narrow rows)  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
 
 // One wavefront per output entry (w, b); per trial, w's neighbours below u_b
@@ -596,15 +599,15 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
             const uint64_t lowb = (1ull << b) - 1ull;
             const uint64_t *rowA = a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & lowb)) * T + lt) * Ca;
             const uint64_t *rowB = a.val + ((grp.dense ? vB * B + b : bB + __popcll(mfB & lowb)) * T + lt) * Ca;
-            for (int c0 = 0; c0 < Ca; c0 += 8) {
-              uint64_t xa[8], xb[8];
+            for (int c0 = 0; c0 < Ca; c0 += EJ_UNROLL) {
+              uint64_t xa[EJ_UNROLL], xb[EJ_UNROLL];
 #pragma unroll
-              for (int q = 0; q < 8; q++) {
+              for (int q = 0; q < EJ_UNROLL; q++) {
                 xa[q] = okA && c0 + q < Ca ? rowA[c0 + q] : 0;
                 xb[q] = okB && c0 + q < Ca ? rowB[c0 + q] : 0;
               }
 #pragma unroll
-              for (int q = 0; q < 8; q++) {
+              for (int q = 0; q < EJ_UNROLL; q++) {
                 if (xa[q]) {
                   const uint32_t R = spread2(s_um[c0 + q], cu, cA);
                   if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * NB + tid], xa[q], of);
