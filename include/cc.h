@@ -185,8 +185,9 @@ cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint6
 
 /*
  * What the calling thread's last cc_count_batch chose for its last query
- * (online tuning when `tuning` was NULL): the trial-group size, the sizes
- * timed and their seconds per colouring, and the number of graph replays.
+ * (online tuning when `tuning` was NULL): the dense cut (the model's, half and
+ * double, one colouring per group) and then the trial-group size, the
+ * candidates timed and their seconds per colouring, and the graph replays.
  */
 typedef struct {
   int32_t trial_group;
@@ -194,6 +195,8 @@ typedef struct {
   int32_t tried_trial_group[8];
   double tried_seconds_per_colouring[8];
   uint64_t graph_replays;
+  int32_t dense_sources;         /* chosen dense cut (sources run as dense groups) */
+  int32_t tried_dense_sources[8];
 } cc_tune_report;
 cc_status cc_last_tune_report(cc_tune_report *out);
 

@@ -250,7 +250,8 @@ def count_batch(g: Graph, queries, seeds, trials, tuning: dict | None = None, st
 class TuneReport(ctypes.Structure):
     _fields_ = [("trial_group", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("tried_trial_group", ctypes.c_int32 * 8), ("tried_seconds_per_colouring", ctypes.c_double * 8),
-                ("graph_replays", ctypes.c_uint64)]
+                ("graph_replays", ctypes.c_uint64), ("dense_sources", ctypes.c_int32),
+                ("tried_dense_sources", ctypes.c_int32 * 8)]
 
 
 def last_tune_report() -> dict:
@@ -258,8 +259,9 @@ def last_tune_report() -> dict:
     r = TuneReport()
     _check(lib().cc_last_tune_report(ctypes.byref(r)))
     n = min(r.candidates, 8)
-    return {"trial_group": r.trial_group, "graph_replays": int(r.graph_replays),
-            "tried": [(r.tried_trial_group[i], r.tried_seconds_per_colouring[i]) for i in range(n)]}
+    return {"trial_group": r.trial_group, "dense_sources": r.dense_sources, "graph_replays": int(r.graph_replays),
+            "tried": [(r.tried_trial_group[i], r.tried_dense_sources[i], r.tried_seconds_per_colouring[i])
+                      for i in range(n)]}
 
 
 class Server:

@@ -239,6 +239,8 @@ cc_status cc_last_tune_report(cc_tune_report *out) {
       out->tried_seconds_per_colouring[i] = r.tried_sec_per_colouring[i];
     }
     out->graph_replays = r.replays;
+    out->dense_sources = r.dense_sources;
+    for (int i = 0; i < 8; i++) out->tried_dense_sources[i] = r.tried_dense[i];
   });
 }
 

@@ -155,6 +155,8 @@ struct TuneReport {
   int trial_group = 0;     // chosen
   int candidates = 0;      // trial-group sizes timed
   int tried_T[8] = {0};
+  int tried_dense[8] = {0};  // dense-group sources of each candidate
+  int dense_sources = 0;     // chosen
   double tried_sec_per_colouring[8] = {0};
   uint64_t replays = 0;    // graph replays by the chosen solver
 };

@@ -626,6 +626,7 @@ class Solver {
   // trials [t0, t0 + Tg) into res (and per_source, indexed [t][orig id])
   void run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountResult &res, std::vector<u128> *per_source);
   int T() const { return z_.T; }
+  int64_t ndense() const { return ndense_; }
   uint64_t graph_replays = 0;
 
  private:
@@ -1360,38 +1361,58 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
   }
   std::unique_ptr<Solver> best;
   double best_per = 0;
-  int cand = 1;
-  while (t0 < trials) {
+  int best_T = 1, best_dense = -1;
+  // one candidate: a solver for (trial group, dense cut), a first group that
+  // learns the hand-backs, a timed replayed group; false when too few trials
+  // are left to time it
+  auto trial = [&](int cand_T, int dense) -> bool {
     ExecOptions o;
     o.use_graphs = 1;
-    o.trial_group = cand;
-    auto S = std::make_unique<Solver>(g, p, std::min(cand, trials), o, st);
+    o.trial_group = cand_T;
+    o.dense_sources = dense;
+    auto S = std::make_unique<Solver>(g, p, std::min(cand_T, trials), o, st);
     const int T = S->T();
-    // group 1: learns the hand-backs (eager); group 2: a timed replay
     S->run_group_of_trials(t0, std::min(T, trials - t0), cs, res, nullptr);
     t0 += std::min(T, trials - t0);
-    if (t0 + T > trials) {  // not enough trials left to time this candidate
+    if (t0 + T > trials) {
       if (!best) best = std::move(S);
-      break;
+      return false;
     }
     auto a = std::chrono::steady_clock::now();
     S->run_group_of_trials(t0, T, cs, res, nullptr);
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
     t0 += T;
+    const int c = std::min(rep.candidates, 7);
     rep.candidates++;
-    rep.tried_T[std::min(rep.candidates, 8) - 1] = T;
-    rep.tried_sec_per_colouring[std::min(rep.candidates, 8) - 1] = dt / T;
-    const bool better = !best || dt / T < best_per;
-    if (better) {
+    rep.tried_T[c] = T;
+    rep.tried_dense[c] = (int)S->ndense();
+    rep.tried_sec_per_colouring[c] = dt / T;
+    if (!best || dt / T < best_per) {
       best_per = dt / T;
+      best_T = T;
+      best_dense = (int)S->ndense();
       best = std::move(S);
     }
-    if (!better || T < cand || T >= 64 || 2 * T > trials - t0) break;
-    cand = 2 * T;
+    return true;
+  };
+  // 1. the dense cut, one colouring per group: the cost model's, half, double
+  if (t0 < trials && trial(1, -1)) {
+    const int d0 = best_dense;
+    for (int d : {d0 / 2, d0 * 2}) {
+      if (d == d0 || t0 >= trials) continue;
+      if (!trial(1, d)) break;
+    }
+  }
+  // 2. the trial-group size at that cut: 2, 4, ... while it keeps improving
+  for (int cand = 2; cand <= 64 && t0 + 2 * cand <= trials; cand *= 2) {
+    const double before = best_per;
+    if (!trial(cand, best_dense)) break;
+    if (best_per >= before) break;
   }
   if (best) {
     for (; t0 < trials; t0 += best->T()) best->run_group_of_trials(t0, std::min(best->T(), trials - t0), cs, res, nullptr);
     rep.trial_group = best->T();
+    rep.dense_sources = (int)best->ndense();
     rep.replays = best->graph_replays;
   }
   g_last_tune = rep;
