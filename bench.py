@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
-    ap.add_argument("--batch-trials", type=int, default=6,
+    ap.add_argument("--batch-trials", type=int, default=12,
                     help="colourings solved in one batched call (0: skip the batched measurement)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run four copies of 1 GiB on the device, so that hardware byte counters "
