@@ -147,7 +147,7 @@ struct RegBuf {
   DevMem val, mask;
 };
 struct LevelBuf {
-  DevMem m, base, list, cnt, bcnt;
+  DevMem mb, list, cnt, bcnt;
 };
 
 int table_C(const Plan &p, int blk) {
@@ -221,7 +221,7 @@ Bytes solver_bytes(const DevGraph &g, const Plan &p, int T) {
   Bytes b;
   b.fixed = table_bytes(g, p, T) + 2 * n * T                   // tables, colours (+ host-colour staging)
             + nregs * 8 * n                                    // activity masks
-            + (uint64_t)dmax * (12 * n + 4 * (n / 4096 + 2))   // level marks and bases
+            + (uint64_t)dmax * (16 * n + 4 * (n / 4096 + 2))   // level marks and bases
             + (uint64_t)light_scratch_bytes(g, T) * light_grid(g.device) + (64 << 20)
             + (large_light_on() ? (uint64_t)(32 << 20) * (light_grid(g.device) / 3) : 0);  // large light stage
   b.per_B = 8 * n * T * slots + (uint64_t)dmax * 8 * n;        // registers, level lists
@@ -660,8 +660,7 @@ class Solver {
   }
   LevelDev leveldev(int d) {
     LevelDev L;
-    L.m = levels_[d].m.as<uint64_t>();
-    L.base = levels_[d].base.as<uint32_t>();
+    L.mb = levels_[d].mb.as<uint64_t>();
     L.list = levels_[d].list.as<int64_t>();
     L.cnt = levels_[d].cnt.as<uint32_t>();
     L.bcnt = levels_[d].bcnt.as<uint32_t>();
@@ -778,9 +777,8 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   const size_t nf_max = (size_t)nlim_max_ * Bmax;
   for (int d = 1; d <= dmax; d++) {
     LevelBuf &L = levels_[d];
-    L.m.alloc(sizeof(uint64_t) * (size_t)nlim_max_);
-    launch_fill_u64(L.m.as<uint64_t>(), nlim_max_, st);
-    L.base.alloc(sizeof(uint32_t) * (size_t)nlim_max_);
+    L.mb.alloc(2 * sizeof(uint64_t) * (size_t)nlim_max_);
+    launch_fill_u64(L.mb.as<uint64_t>(), 2 * nlim_max_, st);
     L.list.alloc(sizeof(int64_t) * nf_max);
     L.cnt.alloc(sizeof(uint32_t));
     L.bcnt.alloc(sizeof(uint32_t) * (size_t)level_chunks(nlim_max_));

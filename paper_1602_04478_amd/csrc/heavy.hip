@@ -51,8 +51,9 @@ __device__ __forceinline__ void entry_vb(const GroupDev &g, const LevelDev &L, i
   }
 }
 __device__ __forceinline__ int64_t sparse_entry(const LevelDev &L, int64_t v, int b) {
-  const uint64_t mm = L.m[v];
-  const int64_t bs = L.base[v];  // loaded together with the marks
+  const ulonglong2 p = ((const ulonglong2 *)L.mb)[v];  // marks and base in one load
+  const uint64_t mm = p.x;
+  const int64_t bs = (int64_t)p.y;
   return ((mm >> b) & 1ull) ? bs + __popcll(mm & ((1ull << b) - 1ull)) : (int64_t)-1;
 }
 __device__ __forceinline__ int64_t entry_of(const GroupDev &g, const LevelDev &L, int64_t v, int b) {
@@ -82,7 +83,7 @@ __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int
     const int b = (int)(i / max_low), j = (int)(i - (int64_t)b * max_low);
     const int64_t u = grp.src[b];
     if (j >= lowcnt[u]) continue;
-    mark(L.m, g.col[g.rp[u] + j], b);
+    mark(L.mb, 2 * (int64_t)g.col[g.rp[u] + j], b);
   }
 }
 
@@ -99,7 +100,7 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
     for (int64_t ee = g.rp[v] + lane; ee < g.rp[v + 1]; ee += TEAM) {
       const int64_t w = g.col[ee];
       if (w >= u) break;
-      mark(Lout.m, w, b);
+      mark(Lout.mb, 2 * w, b);
     }
   }
 }
@@ -121,13 +122,13 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t *s, uint32_t
 }
 
 // marks per chunk (thread t reads vertices lo + i * BLK + t: coalesced)
-__global__ void k_cmp_count(const uint64_t *m, int64_t nv, uint32_t *bcnt) {
+__global__ void k_cmp_count(const uint64_t *mb, int64_t nv, uint32_t *bcnt) {
   __shared__ uint32_t s[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH;
   uint32_t c = 0;
   for (int i = 0; i < CPER; i++) {
     const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
-    if (v < nv) c += __popcll(m[v]);
+    if (v < nv) c += __popcll(mb[2 * v]);
   }
   s[threadIdx.x] = c;
   __syncthreads();
@@ -156,17 +157,17 @@ __global__ void k_cmp_scan(uint32_t *bcnt, int nb, uint32_t *cnt) {
 }
 
 // number the marks: base[v] and the entry list, in (v, b) order
-__global__ void k_cmp_emit(const uint64_t *m, int64_t nv, const uint32_t *boff, uint32_t *base, int64_t *list) {
+__global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64_t *list) {
   __shared__ uint32_t s[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH;
   uint32_t run = boff[blockIdx.x];
   for (int i = 0; i < CPER; i++) {
     const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
-    const uint64_t mm = v < nv ? m[v] : 0;
+    const uint64_t mm = v < nv ? mb[2 * v] : 0;
     uint32_t tot;
     const uint32_t id0 = run + block_scan((uint32_t)__popcll(mm), s, tot);
     if (v < nv) {
-      base[v] = id0;
+      mb[2 * v + 1] = id0;
       uint32_t id = id0;
       for (uint64_t r = mm; r; r &= r - 1) list[id++] = v * 64 + __builtin_ctzll(r);
     }
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
     if (grp.dense) {
       for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_src[i + gl] > w) << i;
     } else {
-      ob = Lout.m[w];
+      ob = Lout.mb[2 * w];
     }
     if (!ob) {
       if (grp.dense && gl == 0)
@@ -530,8 +531,9 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
           if (grp.dense) {
             inb = a.mask[vj];
           } else {
-            mfull = Lin.m[vj];
-            bj = Lin.base[vj];
+            const ulonglong2 p = ((const ulonglong2 *)Lin.mb)[vj];
+            mfull = p.x;
+            bj = (int64_t)p.y;
             inb = mfull;
           }
           inb &= pass;
@@ -1274,9 +1276,9 @@ int fgrid(const GroupDev &grp, int64_t per_entry) {
 static void compact(const GroupDev &grp, LevelDev L, hipStream_t st) {
   const int64_t nv = grp.n_lim;
   const int nb = (int)((nv + CH - 1) / CH);
-  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.m, nv, L.bcnt);
+  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt);
   hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(BLK), 0, st, L.bcnt, nb, L.cnt);
-  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.m, nv, L.bcnt, L.base, L.list);
+  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, L.list);
 }
 
 int64_t level_chunks(int64_t n_lim) { return (n_lim + CH - 1) / CH; }
@@ -1296,7 +1298,9 @@ void launch_level_next(const GraphDev &g, const GroupDev &grp, LevelDev Lin, Lev
 void launch_level_compact(const GroupDev &grp, LevelDev L, hipStream_t st) { compact(grp, L, st); }
 
 // clear the marks for the next group (the list, base and count are rewritten by the next compaction)
-void launch_level_reset(const GroupDev &grp, LevelDev L, hipStream_t st) { launch_fill_u64(L.m, grp.n_lim, st); }
+void launch_level_reset(const GroupDev &grp, LevelDev L, hipStream_t st) {
+  launch_fill_u64(L.mb, 2 * grp.n_lim, st);
+}
 
 void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, int max_low, const uint8_t *colr,
                  LevelDev L, RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st) {

@@ -26,8 +26,8 @@ enum OpKind {
 // entry of (v, b) is v * B + b for every v < n_lim; in sparse mode entries are
 // listed (v * 64 + b) and idx maps (v, b) to its entry or -1.
 struct LevelDev {
-  uint64_t *m;      // [n_lim] bit b of m[v]: (v, b) is an entry
-  uint32_t *base;   // [n_lim] index of v's first entry (entries numbered in (v, b) order)
+  uint64_t *mb;     // [n_lim][2]: marks (bit b: (v, b) is an entry), then the index of v's first
+                    // entry (entries numbered in (v, b) order) -- one 16-byte load per vertex
   int64_t *list;    // [entries] v * 64 + b
   uint32_t *cnt;    // number of entries
   uint32_t *bcnt;   // [chunks] compaction scratch
