@@ -984,9 +984,34 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
     built[d] = 1;
   };
   size_t skip_until = 0;  // steps folded into an earlier launch
+  // A plain NodeJoin whose output is read only as a term of the AXPY chain
+  // right after it is not run on its own: the chain's pass computes its slots
+  // (deferred[r] = the NodeJoin producing r, or -1).
+  std::vector<int> deferred(P.reg_s.size(), -1);
+  auto chain_term_only = [&](size_t si) {
+    const Op &nj = P.ops[steps[si].op];
+    if (si + 1 >= steps.size() || steps[si + 1].fused) return false;
+    const Op &first = P.ops[steps[si + 1].op];
+    if (first.kind != OP_AXPY || !first.first) return false;
+    size_t sj = si + 1;
+    int uses = 0;
+    for (; sj < steps.size() && sj < si + 5 && !steps[sj].fused; sj++) {
+      const Op &o2 = P.ops[steps[sj].op];
+      if (o2.kind != OP_AXPY || o2.dst != first.dst || (sj > si + 1 && o2.first) || o2.a == first.dst) break;
+      uses += o2.a == nj.dst;
+    }
+    int reads = 0;
+    for (auto &o : P.ops)
+      reads += o.a == nj.dst || o.b == nj.dst || (o.kind == OP_AXPY && !o.first && o.dst == nj.dst);
+    return uses >= 1 && uses == reads;
+  };
   for (const Step &stp : steps) {
     if ((size_t)(&stp - steps.data()) < skip_until) continue;
     const Op &op = P.ops[stp.op];
+    if (!stp.fused && op.kind == OP_NJ && chain_term_only((size_t)(&stp - steps.data()))) {
+      deferred[op.dst] = stp.op;
+      continue;
+    }
     static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
                                   "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
     if (op.kind == OP_INIT) build(1);
@@ -1072,18 +1097,33 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
         // a chain dst = w1 a1 + w2 a2 + ... in the next steps runs as one pass
         size_t si = (size_t)(&stp - steps.data());
         if (op.first) {
-          std::vector<RegDev> ta{regdev(op.a)};
-          std::vector<uint64_t> tw{op.w};
+          std::vector<RegDev> ta;
+          std::vector<TabDev> tn;
+          std::vector<uint64_t> tw;
+          bool any_nj = false;
+          auto term = [&](int r, uint64_t w2) {
+            if (deferred[r] >= 0) {  // NodeJoin(x, table) computed in the pass
+              const Op &nj = P.ops[deferred[r]];
+              ta.push_back(regdev(nj.a));
+              tn.push_back(tabdev(nj.tab));
+              any_nj = true;
+            } else {
+              ta.push_back(regdev(r));
+              tn.push_back(TabDev{nullptr, 0, 0});
+            }
+            tw.push_back(w2);
+          };
+          term(op.a, op.w);
           size_t sj = si + 1;
           while (sj < steps.size() && ta.size() < 4 && !steps[sj].fused) {
             const Op &o2 = P.ops[steps[sj].op];
             if (o2.kind != OP_AXPY || o2.first || o2.dst != op.dst || o2.a == op.dst) break;
-            ta.push_back(regdev(o2.a));
-            tw.push_back(o2.w);
+            term(o2.a, o2.w);
             sj++;
           }
-          if (ta.size() > 1) {
-            launch_axpyn(grp, lv(op.a), ta.data(), tw.data(), (int)ta.size(), regdev(op.dst), ovf, st);
+          if (ta.size() > 1 || any_nj) {
+            launch_axpyn(grp, g_.n, colr, lv(op.a), ta.data(), tn.data(), tw.data(), (int)ta.size(), regdev(op.dst),
+                         ovf, st);
             skip_until = sj;
             break;
           }

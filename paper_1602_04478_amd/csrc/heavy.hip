@@ -863,13 +863,46 @@ __global__ __launch_bounds__(BLK) void k_axpy(GroupDev grp, LevelDev L, RegDev a
 }
 
 // dst = sum of w_i * a_i over up to four terms (an AXPY chain in one pass)
+// A term is a register, or the NodeJoin of a register with a node table
+// (then the NodeJoin's output is never stored: its slot is computed here).
 struct AxpyTerms {
   RegDev a[4];
   uint64_t w[4];
+  TabDev nt[4];  // nt[q].val: term q is NodeJoin(a[q], nt[q])
   int n;
 };
-__global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, LevelDev L, AxpyTerms tm, RegDev dst, uint32_t *ovf) {
+
+// slot c (of dst's signature size s) of NodeJoin(a, nt) at row (v, b), trial t
+__device__ __forceinline__ uint64_t nj_slot(const RegDev &a, const TabDev &nt, int64_t row, int64_t v, int t, int T,
+                                            int cu, int cv, uint32_t Rp_unranked, const uint16_t *s_rank, bool &of) {
+  const uint32_t Rp = spread2(Rp_unranked, cu, cv);
+  const uint64_t *ar = a.val + (row * T + t) * a.C;
+  const uint64_t *nr = nt.val + (v * T + t) * nt.C;
+  const int rA = nt.s - 1;
+  uint64_t acc = 0;
+  uint32_t sA = Rp;
+  for (;;) {
+    if (__popc(sA) == rA) {
+      const uint64_t y = nr[s_rank[squeeze1(sA, cv)]];
+      if (y) {
+        const uint64_t x = ar[s_rank[squeeze2(Rp & ~sA, cu, cv)]];
+        if (x) add_ck(acc, mul_ck(x, y, of), of);
+      }
+    }
+    if (sA == 0) break;
+    sA = (sA - 1) & Rp;
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const uint8_t *colr, LevelDev L, AxpyTerms tm,
+                                               RegDev dst, uint32_t *ovf, const uint16_t *lut) {
+  __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_uo[256];  // unranked slots of dst
+  load_rank(s_rank, lut);
   const int T = grp.T, C = dst.C;
+  for (int c = threadIdx.x; c < C; c += BLK) s_uo[c] = unrank(lut, dst.s - 2, c);
+  __syncthreads();
   const int64_t per = (int64_t)T * C;
   const int64_t N = nentries(grp, L) * per;
   uint64_t ofm = 0;
@@ -877,13 +910,24 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, LevelDev L, AxpyTer
     bool of = false;
     uint64_t y = 0;
     const int64_t row = i / per;
+    const int r = (int)(i - row * per), t = r / C, c = r - t * C;
     for (int q = 0; q < tm.n; q++) {
       if (grp.dense && !((tm.a[q].mask[row / grp.B] >> (row % grp.B)) & 1ull)) continue;
-      const uint64_t x = tm.a[q].val[i];
+      uint64_t x;
+      if (tm.nt[q].val) {
+        int64_t v;
+        int b;
+        entry_vb(grp, L, row, v, b);
+        const int64_t u = grp.src[b];
+        const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+        x = (v < u && cu != cv) ? nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of) : 0;
+      } else {
+        x = tm.a[q].val[i];
+      }
       if (x) add_ck(y, mul_ck(tm.w[q], x, of), of);
     }
     dst.val[i] = y;
-    if (of) ofm |= 1ull << ((i / C) % T);
+    if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
 }
@@ -975,8 +1019,14 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
   flag_trials(ovf, ofm);
 }
 
-__global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, AxpyTerms tm, RegDev dst, uint32_t *ovf) {
+__global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, const uint8_t *colr, AxpyTerms tm,
+                                                     RegDev dst, uint32_t *ovf, const uint16_t *lut) {
+  __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_uo[256];  // unranked slots of dst
+  load_rank(s_rank, lut);
   const int T = grp.T, C = dst.C, B = grp.B;
+  for (int c = threadIdx.x; c < C; c += BLK) s_uo[c] = unrank(lut, dst.s - 2, c);
+  __syncthreads();
   const int per = T * C;
   const int lane = threadIdx.x % 64;
   const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
@@ -994,15 +1044,23 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, AxpyTerms tm,
     if (!m) continue;
     const int items = __popcll(m) * per;
     for (int it = lane; it < items; it += 64) {
-      const int q0 = it / per, r = it - q0 * per;
+      const int q0 = it / per, r = it - q0 * per, t = r / C, c = r - t * C;
       const int b = nth_bit(m, q0);
-      const int64_t i = (v * B + b) * per + r;
+      const int64_t row = v * B + b;
+      const int64_t i = row * per + r;
       bool of = false;
       uint64_t y = 0;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         if (q >= tm.n || !((mt[q] >> b) & 1ull)) continue;
-        const uint64_t x = tm.a[q].val[i];
+        uint64_t x;
+        if (tm.nt[q].val) {
+          const int64_t u = grp.src[b];
+          const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+          x = (v < u && cu != cv) ? nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of) : 0;
+        } else {
+          x = tm.a[q].val[i];
+        }
         if (x) add_ck(y, mul_ck(tm.w[q], x, of), of);
       }
       dst.val[i] = y;
@@ -1386,20 +1444,22 @@ void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t
     hipLaunchKernelGGL(k_mask_or, dim3((unsigned)std::min<int64_t>((grp.n_lim + BLK - 1) / BLK, 8192)), dim3(BLK), 0,
                        st, a.mask, dst.mask, grp.n_lim, first);
 }
-void launch_axpyn(const GroupDev &grp, LevelDev L, const RegDev *a, const uint64_t *w, int nterms, RegDev dst,
-                  uint32_t *ovf, hipStream_t st) {
+void launch_axpyn(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev L, const RegDev *a,
+                  const TabDev *nt, const uint64_t *w, int nterms, RegDev dst, uint32_t *ovf, hipStream_t st) {
   AxpyTerms tm{};
   tm.n = nterms;
   for (int q = 0; q < nterms; q++) {
     tm.a[q] = a[q];
     tm.w[q] = w[q];
+    tm.nt[q] = nt ? nt[q] : TabDev{nullptr, 0, 0};
   }
   if (grp.dense) {  // the activity word of dst is written by the same pass
     const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
-    hipLaunchKernelGGL(k_axpyn_dense, dim3(gr), dim3(BLK), 0, st, grp, tm, dst, ovf);
+    hipLaunchKernelGGL(k_axpyn_dense, dim3(gr), dim3(BLK), 0, st, grp, n, colr, tm, dst, ovf, cur_lut());
     return;
   }
-  hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, L, tm, dst, ovf);
+  hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, n, colr, L, tm, dst, ovf,
+                     cur_lut());
 }
 void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
   if (n <= 0) return;

@@ -138,9 +138,10 @@ void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
 void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,
                  hipStream_t st);
 void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st);
-// dst = sum over q < nterms (<= 4) of w[q] * a[q], rows of level L (one pass for an AXPY chain)
-void launch_axpyn(const GroupDev &grp, LevelDev L, const RegDev *a, const uint64_t *w, int nterms, RegDev dst,
-                  uint32_t *ovf, hipStream_t st);
+// dst = sum over q < nterms (<= 4) of w[q] * term q, rows of level L (one pass for an AXPY chain);
+// term q is a[q], or NodeJoin(a[q], nt[q]) when nt && nt[q].val (that NodeJoin's output is not stored)
+void launch_axpyn(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev L, const RegDev *a,
+                  const TabDev *nt, const uint64_t *w, int nterms, RegDev dst, uint32_t *ovf, hipStream_t st);
 void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,
                   uint64_t w, AccDev acc, hipStream_t st);
 void launch_munary(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,
