@@ -705,6 +705,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
     st = st_;
   }
   const int k = p.k;
+  if (!ejmaps_prepare(k)) fail(CC_E_DEVICE, "EdgeJoin slot maps: device allocation failed");
   uint64_t budget = opt.mem_budget ? opt.mem_budget : (uint64_t)(free_bytes() * 0.85);
   z_ = choose(g, p, trials, opt, budget);
   const int T = z_.T;

@@ -24,6 +24,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "kernels.h"
 #include "slot_math.h"
@@ -441,10 +445,15 @@ __host__ __device__ constexpr size_t ejv_lds(int ncols, int nregs, bool epi, int
 }
 constexpr size_t EJV_LDS_MAX = 56 * 1024;
 
-template <bool ANN, int SW, bool EPI, int NB>
+// With MAP, the slot arithmetic of a relaxation (the input row's slot c, the
+// source's colour cu, the neighbour's colour cv and the output vertex's colour
+// cw give the output slot, or none when cw is already used) is read from a
+// table [cu][cv][cw][c] of bytes (0xff: none), four slots per LDS word.
+template <bool ANN, int SW, bool EPI, int NB, bool MAP>
 __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                                               const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
-                                              AccDev accd, const uint16_t *lut) {
+                                              AccDev accd, const uint16_t *lut, const uint32_t *emap, int emap_w,
+                                              int emap_cp) {
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
   __shared__ int32_t s_src[WAVE];
@@ -470,6 +479,9 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
   const int lane = tid % WAVE;
   for (int c = tid; c < W; c += NB) s_um[c] = unrank(lut, ANN ? ro : ra, c);
   if (tid < WAVE) s_src[tid] = tid < B ? grp.src[tid] : -1;
+  uint32_t *const s_map = (uint32_t *)((char *)accs + ejv_lds(epi.ncols, epi.nregs, EPI, NB));
+  if (MAP)
+    for (int i = tid; i < emap_w; i += NB) s_map[i] = emap[i];
   __syncthreads();
   constexpr int NG = WAVE / SW;  // groups per wavefront
   const int gl = lane % SW, gbase = lane - gl;
@@ -562,15 +574,22 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
             n_rows++;
             const uint64_t *rowA =
                 a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & ((1ull << b) - 1ull))) * T + lt) * Ca;
+            const uint32_t *mA = s_map + ((cu * grp.k + cA) * grp.k + cw) * (emap_cp >> 2);
             for (int c0 = 0; c0 < Ca; c0 += 4) {
               uint64_t xa[4];
 #pragma unroll
               for (int q = 0; q < 4; q++) xa[q] = c0 + q < Ca ? rowA[c0 + q] : 0;
+              const uint32_t mw = MAP ? mA[c0 >> 2] : 0;
 #pragma unroll
               for (int q = 0; q < 4; q++) {
                 if (!xa[q]) continue;
-                const uint32_t R = spread2(s_um[c0 + q], cu, cA);
-                if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * NB + tid], xa[q], of);
+                if (MAP) {
+                  const uint32_t o = (mw >> (8 * q)) & 0xffu;
+                  if (o != 0xffu) add_ck(acc[o * NB + tid], xa[q], of);
+                } else {
+                  const uint32_t R = spread2(s_um[c0 + q], cu, cA);
+                  if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * NB + tid], xa[q], of);
+                }
               }
             }
           }
@@ -601,6 +620,8 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
             const uint64_t lowb = (1ull << b) - 1ull;
             const uint64_t *rowA = a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & lowb)) * T + lt) * Ca;
             const uint64_t *rowB = a.val + ((grp.dense ? vB * B + b : bB + __popcll(mfB & lowb)) * T + lt) * Ca;
+            const uint32_t *mA = s_map + ((cu * grp.k + cA) * grp.k + cw) * (emap_cp >> 2);
+            const uint32_t *mB = s_map + ((cu * grp.k + cB) * grp.k + cw) * (emap_cp >> 2);
             for (int c0 = 0; c0 < Ca; c0 += EJ_UNROLL) {
               uint64_t xa[EJ_UNROLL], xb[EJ_UNROLL];
 #pragma unroll
@@ -608,8 +629,16 @@ __global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint
                 xa[q] = okA && c0 + q < Ca ? rowA[c0 + q] : 0;
                 xb[q] = okB && c0 + q < Ca ? rowB[c0 + q] : 0;
               }
+              static_assert(!MAP || EJ_UNROLL == 4, "map words hold four slots");
+              const uint32_t mwA = MAP ? mA[c0 >> 2] : 0, mwB = MAP ? mB[c0 >> 2] : 0;
 #pragma unroll
               for (int q = 0; q < EJ_UNROLL; q++) {
+                if (MAP) {
+                  const uint32_t oA = (mwA >> (8 * q)) & 0xffu, oB = (mwB >> (8 * q)) & 0xffu;
+                  if (xa[q] && oA != 0xffu) add_ck(acc[oA * NB + tid], xa[q], of);
+                  if (xb[q] && oB != 0xffu) add_ck(acc[oB * NB + tid], xb[q], of);
+                  continue;
+                }
                 if (xa[q]) {
                   const uint32_t R = spread2(s_um[c0 + q], cu, cA);
                   if (!((R >> cw) & 1u)) add_ck(acc[s_rank[squeeze2(R | (1u << cA), cu, cw)] * NB + tid], xa[q], of);
@@ -1372,32 +1401,127 @@ bool epi_fits(int ncols, int T, int etab_C) {
   return ncols <= VMAX_C && T <= WAVE && etab_C <= 256 && ejv_lds(ncols, EPI_MAX_REGS, true, WAVE) <= EJV_LDS_MAX;
 }
 
+// EdgeJoin slot maps: for colours k and input rank ra (slots of the input
+// rows: C(k-2, ra)), entry [cu][cv][cw][c] is the output slot of input slot
+// c when the path from a source of colour cu steps from a vertex of colour cv
+// to one of colour cw -- the rank of (R + cv) with cu and cw squeezed out,
+// where R is slot c's colour set spread around cu and cv -- or 0xff when cw is
+// in R or the three colours are not distinct.  Rows padded to four slots.
+// Built on the host once per device and k, kept until the process ends.
+constexpr size_t EJMAP_MAX = 16384;  // bytes of one map (it is copied into LDS)
+namespace {
+struct EjMaps {
+  uint32_t *d[12] = {};
+  int words[12] = {}, cp[12] = {}, ca[12] = {};
+};
+std::mutex ejm_mu;
+std::map<std::pair<int, int>, EjMaps> ejm;
+
+int host_binom(int n, int r) {
+  if (r < 0 || r > n) return 0;
+  long c = 1;
+  for (int i = 1; i <= r; i++) c = c * (n - r + i) / i;
+  return (int)c;
+}
+int host_rank(uint32_t m) {  // colex rank among masks of the same popcount
+  int idx = 0, i = 0;
+  for (int p = 0; p < 32; p++)
+    if ((m >> p) & 1u) idx += host_binom(p, ++i);
+  return idx;
+}
+}  // namespace
+
+bool ejmaps_prepare(int k) {
+  if (k < 3 || k > 12) return true;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(ejm_mu);
+  if (ejm.count({dev, k})) return true;
+  EjMaps M;
+  for (int ra = 0; ra <= k - 2; ra++) {
+    const int ca = host_binom(k - 2, ra), cp = (ca + 3) & ~3;
+    const size_t bytes = (size_t)k * k * k * cp;
+    if (bytes > EJMAP_MAX || host_binom(k - 2, ra + 1) > 255) continue;
+    std::vector<uint32_t> um(ca);
+    for (uint32_t m = 0; m < (1u << (k - 2)); m++)
+      if (__builtin_popcount(m) == ra) um[host_rank(m)] = m;
+    std::vector<uint8_t> h(bytes, 0xff);
+    for (int cu = 0; cu < k; cu++)
+      for (int cv = 0; cv < k; cv++)
+        for (int cw = 0; cw < k; cw++) {
+          if (cu == cv || cu == cw || cv == cw) continue;
+          uint8_t *row = &h[(((size_t)cu * k + cv) * k + cw) * cp];
+          for (int c = 0; c < ca; c++) {
+            const uint32_t R = dev::spread2(um[c], cu, cv);
+            if ((R >> cw) & 1u) continue;
+            row[c] = (uint8_t)host_rank(dev::squeeze2(R | (1u << cv), cu, cw));
+          }
+        }
+    uint32_t *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return false;
+    if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+    M.d[ra] = d;
+    M.words[ra] = (int)(bytes / 4);
+    M.cp[ra] = cp;
+    M.ca[ra] = ca;
+  }
+  ejm[{dev, k}] = M;
+  return true;
+}
+
+static bool getenv_flag_off(const char *name) {
+  const char *e = std::getenv(name);
+  return e && e[0] == '0';
+}
+
+// the prepared map for (k, ra) on the current device, if any (allocates nothing)
+static bool ejmap_find(int k, int ra, int ca, const uint32_t **p, int *words, int *cp) {
+  if (ra < 0 || ra > 11) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(ejm_mu);
+  auto it = ejm.find({dev, k});
+  if (it == ejm.end() || !it->second.d[ra] || it->second.ca[ra] != ca) return false;
+  *p = it->second.d[ra];
+  *words = it->second.words[ra];
+  *cp = it->second.cp[ra];
+  return true;
+}
+
 void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                    const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st) {
   const bool ep = epi.nops > 0;
+  const uint32_t *em = nullptr;
+  int emw = 0, emcp = 0;
+  const bool mp = !etab.val && !getenv_flag_off("CC_EJMAP") && ejmap_find(grp.k, a.s - 2, a.C, &em, &emw, &emcp);
+  const size_t mapb = mp ? (size_t)emw * 4 : 0;
   // four wavefronts per workgroup when their LDS columns fit, else one
-  const bool wide = ejv_lds(epi.ncols, epi.nregs, ep, EJ_BLK) <= EJV_LDS_MAX;
+  const bool wide = ejv_lds(epi.ncols, epi.nregs, ep, EJ_BLK) + mapb <= EJV_LDS_MAX;
   const int nb = wide ? EJ_BLK : WAVE;
-  const size_t lds = ejv_lds(epi.ncols, epi.nregs, ep, nb);
+  const size_t lds = ejv_lds(epi.ncols, epi.nregs, ep, nb) + mapb;
   // sparse groups meet few sources per vertex: four vertices per wavefront
   const bool quarter = !grp.dense && grp.T <= 16;
   const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;  // wavefronts' worth of vertices
   const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((nw + nb / WAVE - 1) / (nb / WAVE), 32768 / (nb / WAVE)));
-#define CC_EJV(ANN_, SW_, EPI_, NB_)                                                                          \
-  hipLaunchKernelGGL((k_ejv<ANN_, SW_, EPI_, NB_>), dim3(gr), dim3(NB_), lds, st, g, grp, colr, Lin, a, epi, etab, \
-                     e_src_first, ovf, acc, cur_lut())
-#define CC_EJV2(ANN_, SW_, EPI_) \
-  if (wide) CC_EJV(ANN_, SW_, EPI_, EJ_BLK); else CC_EJV(ANN_, SW_, EPI_, WAVE)
-  const int sel = (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
+#define CC_EJV(ANN_, SW_, EPI_, NB_, MAP_)                                                                   \
+  hipLaunchKernelGGL((k_ejv<ANN_, SW_, EPI_, NB_, MAP_>), dim3(gr), dim3(NB_), lds, st, g, grp, colr, Lin, a, epi, \
+                     etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp)
+#define CC_EJV2(ANN_, SW_, EPI_, MAP_) \
+  if (wide) CC_EJV(ANN_, SW_, EPI_, EJ_BLK, MAP_); else CC_EJV(ANN_, SW_, EPI_, WAVE, MAP_)
+  const int sel = (mp ? 8 : 0) | (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
   switch (sel) {
-    case 0: CC_EJV2(false, 64, false); break;
-    case 1: CC_EJV2(false, 64, true); break;
-    case 2: CC_EJV2(false, 16, false); break;
-    case 3: CC_EJV2(false, 16, true); break;
-    case 4: CC_EJV2(true, 64, false); break;
-    case 5: CC_EJV2(true, 64, true); break;
-    case 6: CC_EJV2(true, 16, false); break;
-    default: CC_EJV2(true, 16, true); break;
+    case 0: CC_EJV2(false, 64, false, false); break;
+    case 1: CC_EJV2(false, 64, true, false); break;
+    case 2: CC_EJV2(false, 16, false, false); break;
+    case 3: CC_EJV2(false, 16, true, false); break;
+    case 4: CC_EJV2(true, 64, false, false); break;
+    case 5: CC_EJV2(true, 64, true, false); break;
+    case 6: CC_EJV2(true, 16, false, false); break;
+    case 7: CC_EJV2(true, 16, true, false); break;
+    case 8: CC_EJV2(false, 64, false, true); break;
+    case 9: CC_EJV2(false, 64, true, true); break;
+    case 10: CC_EJV2(false, 16, false, true); break;
+    default: CC_EJV2(false, 16, true, true); break;
   }
 #undef CC_EJV2
 #undef CC_EJV

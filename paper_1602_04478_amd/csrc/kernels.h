@@ -133,6 +133,9 @@ void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
 void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                    const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st);
 bool epi_fits(int ncols, int T, int etab_C);
+// build (once per device and k) the EdgeJoin slot maps the vertex-major kernel
+// reads instead of the slot arithmetic; false on a device error
+bool ejmaps_prepare(int k);
 void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev L, RegDev a, RegDev dst,
                TabDev ntab, uint32_t *ovf, hipStream_t st);
 void launch_axpy(const GroupDev &grp, LevelDev L, RegDev a, RegDev dst, uint64_t w, int first, uint32_t *ovf,

@@ -16,14 +16,14 @@ namespace dev {
 constexpr int BLK = 256;
 constexpr int LUT_RANK = 0, LUT_UNRANK = 2048, LUT_OFF = 4096, LUT_SIZE = 4112;
 
-__device__ __forceinline__ uint32_t squeeze2(uint32_t m, int c1, int c2) {
+__host__ __device__ __forceinline__ uint32_t squeeze2(uint32_t m, int c1, int c2) {
   int lo = min(c1, c2), hi = max(c1, c2);
   uint32_t a = m & ((1u << lo) - 1u);
   uint32_t b = (m >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1u);
   uint32_t c = m >> (hi + 1);
   return a | (b << lo) | (c << (hi - 1));
 }
-__device__ __forceinline__ uint32_t spread2(uint32_t m, int c1, int c2) {
+__host__ __device__ __forceinline__ uint32_t spread2(uint32_t m, int c1, int c2) {
   int lo = min(c1, c2), hi = max(c1, c2);
   uint32_t a = m & ((1u << lo) - 1u);
   uint32_t b = (m >> lo) & ((1u << (hi - lo - 1)) - 1u);
