@@ -231,11 +231,19 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
 // dst[(w,b)][R'] = sum over v in N(w), v < u_b, (v,b) an entry of the lower
 // level, of sum over splits R' \ {chi v} = R + Re of a[(v,b)][R] * E(v,w)[Re].
 constexpr int WAVE = 64;
-constexpr int VMAX_C = 96;
+constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
+// wavefronts per SIMD the vertex-major EdgeJoin asks of the register
+// allocator (with slot maps and no epilogue): 96 registers give five
+#ifndef EJ_MINW_SPARSE
+#define EJ_MINW_SPARSE 5
+#endif
+#ifndef EJ_MINW_DENSE
+#define EJ_MINW_DENSE 1
+#endif
 #ifndef EJ_UNROLL
 #define EJ_UNROLL 4  // slots of both rows loaded before they are added (two-neighbour steps)
 #endif
-constexpr int EJ_BLK = 256;  // four wavefronts per workgroup share the rank tables (narrow rows)  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
+constexpr int EJ_BLK = 256;  // four wavefronts per workgroup share the rank tables (narrow rows)
 
 // One wavefront per output entry (w, b); per trial, w's neighbours below u_b
 // are taken 64 at a time in two phases:
@@ -450,7 +458,7 @@ constexpr size_t EJV_LDS_MAX = 56 * 1024;
 // cw give the output slot, or none when cw is already used) is read from a
 // table [cu][cv][cw][c] of bytes (0xff: none), four slots per LDS word.
 template <bool ANN, int SW, bool EPI, int NB, bool MAP>
-__global__ __launch_bounds__(NB) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
+__global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_MINW_DENSE) : 1) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                                               const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
                                               AccDev accd, const uint16_t *lut, const uint32_t *emap, int emap_w,
                                               int emap_cp) {
@@ -1105,15 +1113,16 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
 __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const uint8_t *colr, LevelDev La,
                                                LevelDev Lb, RegDev a, RegDev bb, uint64_t w, AccDev acc,
                                                const uint16_t *lut) {
-  __shared__ uint16_t s_rank[2048];
-  __shared__ uint32_t s_ua[256];  // unranked slots of a
+  // The partner slot of a's slot c does not depend on the colours: with cu
+  // and cv squeezed out, K minus {cu, cv} minus R is the complement of c's
+  // colour set in k - 2 bits.
+  __shared__ uint16_t s_yi[256];  // b's slot partnering a's slot c
   __shared__ uint64_t s_acc[2 * 64];
   for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) s_acc[i] = 0;
-  load_rank(s_rank, lut);
   const int T = grp.T, Ca = a.C, Cb = bb.C, k = grp.k;
-  for (int c = threadIdx.x; c < Ca; c += BLK) s_ua[c] = unrank(lut, a.s - 2, c);
+  const uint32_t Kp = (1u << (k - 2)) - 1u;
+  for (int c = threadIdx.x; c < Ca; c += BLK) s_yi[c] = lut[LUT_RANK + (Kp & ~unrank(lut, a.s - 2, c))];
   __syncthreads();
-  const uint32_t Kmask = (1u << k) - 1u;
   const int64_t N = nentries(grp, La);
   for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < N; e += (int64_t)gridDim.x * BLK) {
     int64_t v;
@@ -1133,9 +1142,7 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
       for (int c = 0; c < Ca; c++) {
         const uint64_t x = ar[c];
         if (!x) continue;
-        const uint32_t R1 = spread2(s_ua[c], cu, cv);
-        const uint32_t R2 = Kmask & ~R1 & ~(1u << cu) & ~(1u << cv);
-        const uint64_t y = br[s_rank[squeeze2(R2, cu, cv)]];
+        const uint64_t y = br[s_yi[c]];
         if (!y) continue;
         uint64_t pl = x * y, ph = __umul64hi(x, y);
         if (w != 1) {
