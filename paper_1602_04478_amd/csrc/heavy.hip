@@ -231,14 +231,15 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
 // dst[(w,b)][R'] = sum over v in N(w), v < u_b, (v,b) an entry of the lower
 // level, of sum over splits R' \ {chi v} = R + Re of a[(v,b)][R] * E(v,w)[Re].
 constexpr int WAVE = 64;
+constexpr int VNONE = 0x7fffffff;  // no vertex (ids are below 2^31)
 constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps an LDS column per lane
 // wavefronts per SIMD the vertex-major EdgeJoin asks of the register
-// allocator (with slot maps and no epilogue): 96 registers give five
+// allocator (with slot maps and no epilogue): at most 96 registers, five
 #ifndef EJ_MINW_SPARSE
 #define EJ_MINW_SPARSE 5
 #endif
 #ifndef EJ_MINW_DENSE
-#define EJ_MINW_DENSE 1
+#define EJ_MINW_DENSE 5
 #endif
 #ifndef EJ_UNROLL
 #define EJ_UNROLL 4  // slots of both rows loaded before they are added (two-neighbour steps)
@@ -499,17 +500,20 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
   const int lt = gl % T, lb = gl / T;    // lane's trial, its source's slot in the pass
   const int64_t n = g.n;
   const uint32_t Kmask = (1u << grp.k) - 1u;
-  uint64_t ofm = 0, n_scan = 0, n_rows = 0, n_ent = 0;
+  uint64_t ofm = 0;
+  uint32_t n_scan = 0, n_rows = 0, n_ent = 0;  // profile counts of this lane (each below 2^32 per launch)
   uint64_t mlo = 0, mhi = 0;  // this lane's root-merge sum (its trial)
   constexpr int WPB = NB / WAVE;  // wavefronts per workgroup
-  for (int64_t w = ((int64_t)blockIdx.x * WPB + tid / WAVE) * NG + lane / SW; w < grp.n_lim;
-       w += (int64_t)gridDim.x * WPB * NG) {
+  // vertex ids fit 31 bits (the graph's limit), so they travel as int
+  const uint32_t nlim = (uint32_t)grp.n_lim, wstride = gridDim.x * WPB * NG;
+  for (uint32_t wl = (blockIdx.x * WPB + tid / WAVE) * NG + lane / SW; wl < nlim; wl += wstride) {
+    const int w = (int)wl;
     // output rows at w: dense -- every source above w; sparse -- the marks
     uint64_t ob = 0;
     if (grp.dense) {
       for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_src[i + gl] > w) << i;
     } else {
-      ob = Lout.mb[2 * w];
+      ob = Lout.mb[2 * (int64_t)w];
     }
     if (!ob) {
       if (grp.dense && gl == 0)
@@ -529,9 +533,9 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
       const uint64_t pass = last == 63 ? rest : rest & ((1ull << (last + 1)) - 1ull);
       rest &= ~pass;
       const int b = lb < np ? nth_set_bit(pass, lb) : -1;
-      const int64_t u = b >= 0 ? s_src[b] : 0;
-      int64_t umax = u;  // the neighbours below the pass's largest source
-      for (int o = SW / 2; o > 0; o >>= 1) umax = max(umax, (int64_t)__shfl_xor(umax, o, SW));
+      const int u = b >= 0 ? s_src[b] : 0;
+      int umax = u;  // the neighbours below the pass's largest source
+      for (int o = SW / 2; o > 0; o >>= 1) umax = max(umax, __shfl_xor(umax, o, SW));
       int cu = 0, cw = 0;
       bool act = false;
       if (b >= 0) {
@@ -543,11 +547,11 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
       bool of = false;
       for (int64_t j0 = r0; j0 < r1; j0 += SW) {
         const int64_t ee = j0 + gl;
-        int64_t vj = ee < r1 ? g.col[ee] : INT64_MAX;
-        if (vj >= umax) vj = INT64_MAX;
+        int vj = ee < r1 ? g.col[ee] : VNONE;
+        if (vj >= umax) vj = VNONE;
         uint64_t inb = 0, mfull = 0;
         int64_t bj = 0;
-        if (vj != INT64_MAX) {
+        if (vj != VNONE) {
           if (grp.dense) {
             inb = a.mask[vj];
           } else {
@@ -558,10 +562,10 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           }
           inb &= pass;
         }
-        const uint64_t below = gballot(vj != INT64_MAX);
-        n_scan += act ? (uint64_t)__popcll(below) : 0;
+        const uint64_t below = gballot(vj != VNONE);
+        n_scan += act ? (uint32_t)__popcll(below) : 0u;
         uint64_t todo = gballot(inb != 0);
-        const bool stop = gballot(vj == INT64_MAX) != 0;
+        const bool stop = gballot(vj == VNONE) != 0;
         // one trial: the neighbour's colour travels with it (loaded by its own lane)
         const int cvj = (T == 1 && inb) ? colr[vj] : 0;
         if (!ANN && SW < 64) {
@@ -570,7 +574,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           while (todo) {
             const int jA = __builtin_ctzll(todo);
             todo &= todo - 1;
-            const int64_t vA = __shfl(vj, jA, SW);
+            const int vA = __shfl(vj, jA, SW);
             const uint64_t ibA = __shfl(inb, jA, SW);
             const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA, SW);
             const int64_t bA = grp.dense ? 0 : __shfl(bj, jA, SW);
@@ -581,7 +585,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
             if (!okA) continue;
             n_rows++;
             const uint64_t *rowA =
-                a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & ((1ull << b) - 1ull))) * T + lt) * Ca;
+                a.val + ((grp.dense ? (int64_t)vA * B + b : bA + __popcll(mfA & ((1ull << b) - 1ull))) * T + lt) * Ca;
             const uint32_t *mA = s_map + ((cu * grp.k + cA) * grp.k + cw) * (emap_cp >> 2);
             for (int c0 = 0; c0 < Ca; c0 += 4) {
               uint64_t xa[4];
@@ -610,7 +614,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
             if (todo) todo &= todo - 1;
             const bool hasB = jB != jA;
             // every lane of the group takes part in the cross-lane reads
-            const int64_t vA = __shfl(vj, jA, SW), vB = __shfl(vj, jB, SW);
+            const int vA = __shfl(vj, jA, SW), vB = __shfl(vj, jB, SW);
             const uint64_t ibA = __shfl(inb, jA, SW), ibB = __shfl(inb, jB, SW);
             const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA, SW), mfB = grp.dense ? 0 : __shfl(mfull, jB, SW);
             const int64_t bA = grp.dense ? 0 : __shfl(bj, jA, SW), bB = grp.dense ? 0 : __shfl(bj, jB, SW);
@@ -624,10 +628,12 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
             okA = okA && cA != cu && cA != cw;
             okB = okB && cB != cu && cB != cw;
             if (!okA && !okB) continue;
-            n_rows += (uint64_t)okA + (uint64_t)okB;
+            n_rows += (uint32_t)okA + (uint32_t)okB;
             const uint64_t lowb = (1ull << b) - 1ull;
-            const uint64_t *rowA = a.val + ((grp.dense ? vA * B + b : bA + __popcll(mfA & lowb)) * T + lt) * Ca;
-            const uint64_t *rowB = a.val + ((grp.dense ? vB * B + b : bB + __popcll(mfB & lowb)) * T + lt) * Ca;
+            const uint64_t *rowA =
+                a.val + ((grp.dense ? (int64_t)vA * B + b : bA + __popcll(mfA & lowb)) * T + lt) * Ca;
+            const uint64_t *rowB =
+                a.val + ((grp.dense ? (int64_t)vB * B + b : bB + __popcll(mfB & lowb)) * T + lt) * Ca;
             const uint32_t *mA = s_map + ((cu * grp.k + cA) * grp.k + cw) * (emap_cp >> 2);
             const uint32_t *mB = s_map + ((cu * grp.k + cB) * grp.k + cw) * (emap_cp >> 2);
             for (int c0 = 0; c0 < Ca; c0 += EJ_UNROLL) {
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           while (todo) {
             const int jj = __builtin_ctzll(todo);
             todo &= todo - 1;
-            const int64_t v = __shfl(vj, jj, SW);
+            const int v = __shfl(vj, jj, SW);
             const uint64_t ib = __shfl(inb, jj, SW);
             const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj, SW);
             const int64_t vb = grp.dense ? 0 : __shfl(bj, jj, SW);
@@ -670,7 +676,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
             if (!act || v >= u || !((ib >> b) & 1ull)) continue;
             const int cv = T == 1 ? cvs : colr[(int64_t)lt * n + v];
             if (cv == cu || cv == cw) continue;
-            const int64_t id = grp.dense ? v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
+            const int64_t id = grp.dense ? (int64_t)v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
             n_rows++;
             const uint64_t *row = a.val + (id * T + lt) * Ca;
             const int64_t es = j0 + jj;
@@ -706,7 +712,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           const EpiReg &R = epi.regs[j];
           int64_t id = -1;
           if (R.col < 0) {
-            if (grp.dense) id = ((R.r.mask[w] >> b) & 1ull) ? w * B + b : -1;
+            if (grp.dense) id = ((R.r.mask[w] >> b) & 1ull) ? (int64_t)w * B + b : -1;
             else id = sparse_entry(R.L, w, b);
           }
           s_rid[j * NB + tid] = id;
@@ -727,7 +733,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
               uint64_t v = 0;
               if (cu != cw) {
                 const uint32_t Rp = spread2(unr(D.r.s - 2, c), cu, cw);
-                const uint64_t *nr = op.nt.val + (w * T + lt) * op.nt.C;
+                const uint64_t *nr = op.nt.val + ((int64_t)w * T + lt) * op.nt.C;
                 uint32_t sA = Rp;
                 for (;;) {
                   if (__popc(sA) == rA) {
@@ -768,7 +774,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
                 pl = l2;
                 ph = h2;
               }
-              if (accd.per_src) atomic_add128(&accd.per_src[2 * (u * T + lt)], pl, ph);
+              if (accd.per_src) atomic_add128(&accd.per_src[2 * ((int64_t)u * T + lt)], pl, ph);
               const uint64_t sl = mlo + pl;
               mhi += ph + (sl < pl ? 1u : 0u);
               mlo = sl;
@@ -794,7 +800,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           for (int o = SW / 2; o > 0; o >>= 1) mine |= (uint64_t)__shfl_xor(mine, o, SW);
         if (grp.dense && gl == 0) s_live[j * (NB / SW) + tid / SW] |= mine;
         if (b >= 0 && (!grp.dense || ((mine >> b) & 1ull))) {
-          const int64_t id = grp.dense ? w * B + b : sparse_entry(R.L, w, b);
+          const int64_t id = grp.dense ? (int64_t)w * B + b : sparse_entry(R.L, w, b);
           uint64_t *drow = R.r.val + (id * T + lt) * Cj;
           for (int o = 0; o < Cj; o++) drow[o] = accs[(R.col + o) * NB + tid];
         }
@@ -804,7 +810,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
       if (grp.dense)
         for (int j = 0; j < epi.nregs; j++)
           if (epi.regs[j].write) epi.regs[j].r.mask[w] = s_live[j * (NB / SW) + tid / SW];
-      n_ent += __popcll(ob);
+      n_ent += (uint32_t)__popcll(ob);
     }
   }
   flag_trials(ovf, ofm);
@@ -815,16 +821,17 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
       atomic_add128(&accd.sum[2 * tid], s_msum[2 * tid], s_msum[2 * tid + 1]);
   }
   if (grp.prof) {
+    uint64_t c0 = n_scan, c1 = n_rows, c2 = n_ent;
     for (int o = 32; o > 0; o >>= 1) {
-      n_scan += __shfl_xor(n_scan, o);
-      n_rows += __shfl_xor(n_rows, o);
-      n_ent += __shfl_xor(n_ent, o);
+      c0 += __shfl_xor(c0, o);
+      c1 += __shfl_xor(c1, o);
+      c2 += __shfl_xor(c2, o);
     }
     if (lane == 0) {
       uint64_t *pc = grp.prof + 3 * ((blockIdx.x * WPB + tid / WAVE) % PROF_LANES);  // spread over lanes: no hot address
-      atomicAdd((unsigned long long *)&pc[0], (unsigned long long)n_scan);
-      atomicAdd((unsigned long long *)&pc[1], (unsigned long long)n_rows);
-      atomicAdd((unsigned long long *)&pc[2], (unsigned long long)n_ent);
+      atomicAdd((unsigned long long *)&pc[0], (unsigned long long)c0);
+      atomicAdd((unsigned long long *)&pc[1], (unsigned long long)c1);
+      atomicAdd((unsigned long long *)&pc[2], (unsigned long long)c2);
     }
   }
 }
