@@ -912,9 +912,41 @@ __global__ __launch_bounds__(BLK) void k_axpy(GroupDev grp, LevelDev L, RegDev a
 struct AxpyTerms {
   RegDev a[4];
   uint64_t w[4];
-  TabDev nt[4];  // nt[q].val: term q is NodeJoin(a[q], nt[q])
+  TabDev nt[4];          // nt[q].val: term q is NodeJoin(a[q], nt[q])
+  const uint32_t *jm[4];  // NodeJoin split map of term q (or null), jmw[q] words, jns[q] splits per slot
+  int jmw[4], jns[4];
   int n;
 };
+
+// NodeJoin splits from a map.  For output slot c (colour set S of dst, cu and
+// cv squeezed out) the splits are the subsets S_j of S of nt's size: xi[j] is
+// the slot of S minus S_j in a (it does not depend on the colours), yi[j] the
+// slot of S_j in nt's row, where only the position of cu among the k - 1
+// colours other than cv matters (cu' = cu - [cv < cu]).
+__device__ __forceinline__ uint64_t nj_slot_map(const uint64_t *ar, const uint64_t *nr, const uint8_t *xi,
+                                                const uint16_t *yi, int ns, bool &of) {
+  uint64_t acc = 0;
+  for (int j = 0; j < ns; j++) {
+    const uint64_t y = nr[yi[j]];
+    if (!y) continue;
+    const uint64_t x = ar[xi[j]];
+    if (x) add_ck(acc, mul_ck(x, y, of), of);
+  }
+  return acc;
+}
+// LDS copies of the split maps of the terms, one after another
+__device__ __forceinline__ void load_jmaps(const AxpyTerms &tm, uint32_t *s_jm) {
+  int off = 0;
+  for (int q = 0; q < tm.n; q++) {
+    for (int i = threadIdx.x; i < tm.jmw[q]; i += blockDim.x) s_jm[off + i] = tm.jm[q][i];
+    off += tm.jmw[q];
+  }
+}
+__device__ __forceinline__ const uint32_t *jmap_at(const AxpyTerms &tm, const uint32_t *s_jm, int q) {
+  int off = 0;
+  for (int p = 0; p < q; p++) off += tm.jmw[p];
+  return s_jm + off;
+}
 
 // slot c (of dst's signature size s) of NodeJoin(a, nt) at row (v, b), trial t
 __device__ __forceinline__ uint64_t nj_slot(const RegDev &a, const TabDev &nt, int64_t row, int64_t v, int t, int T,
@@ -943,6 +975,8 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
                                                RegDev dst, uint32_t *ovf, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_uo[256];  // unranked slots of dst
+  extern __shared__ uint32_t s_jm[];
+  load_jmaps(tm, s_jm);
   load_rank(s_rank, lut);
   const int T = grp.T, C = dst.C;
   for (int c = threadIdx.x; c < C; c += BLK) s_uo[c] = unrank(lut, dst.s - 2, c);
@@ -964,7 +998,18 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
         entry_vb(grp, L, row, v, b);
         const int64_t u = grp.src[b];
         const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
-        x = (v < u && cu != cv) ? nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of) : 0;
+        x = 0;
+        if (v < u && cu != cv) {
+          if (tm.jmw[q]) {
+            const int ns = tm.jns[q];
+            const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
+            const uint16_t *yi = (const uint16_t *)(jmap_at(tm, s_jm, q) + ((C * ns + 3) >> 2)) + ((cu - (cv < cu)) * C + c) * ns;
+            x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi, yi,
+                            ns, of);
+          } else {
+            x = nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of);
+          }
+        }
       } else {
         x = tm.a[q].val[i];
       }
@@ -1067,6 +1112,8 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
                                                      RegDev dst, uint32_t *ovf, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_uo[256];  // unranked slots of dst
+  extern __shared__ uint32_t s_jm[];
+  load_jmaps(tm, s_jm);
   load_rank(s_rank, lut);
   const int T = grp.T, C = dst.C, B = grp.B;
   for (int c = threadIdx.x; c < C; c += BLK) s_uo[c] = unrank(lut, dst.s - 2, c);
@@ -1101,7 +1148,18 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
         if (tm.nt[q].val) {
           const int64_t u = grp.src[b];
           const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
-          x = (v < u && cu != cv) ? nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of) : 0;
+          x = 0;
+          if (v < u && cu != cv) {
+            if (tm.jmw[q]) {
+              const int ns = tm.jns[q];
+              const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
+              const uint16_t *yi = (const uint16_t *)(jmap_at(tm, s_jm, q) + ((C * ns + 3) >> 2)) + ((cu - (cv < cu)) * C + c) * ns;
+              x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi,
+                              yi, ns, of);
+            } else {
+              x = nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of);
+            }
+          }
         } else {
           x = tm.a[q].val[i];
         }
@@ -1445,11 +1503,14 @@ int host_rank(uint32_t m) {  // colex rank among masks of the same popcount
 }
 }  // namespace
 
+static bool njmaps_build(int dev, int k);
+
 bool ejmaps_prepare(int k) {
   if (k < 3 || k > 12) return true;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   std::lock_guard<std::mutex> lk(ejm_mu);
+  if (!njmaps_build(dev, k)) return false;
   if (ejm.count({dev, k})) return true;
   EjMaps M;
   for (int ra = 0; ra <= k - 2; ra++) {
@@ -1499,6 +1560,71 @@ static bool ejmap_find(int k, int ra, int ca, const uint32_t **p, int *words, in
   *p = it->second.d[ra];
   *words = it->second.words[ra];
   *cp = it->second.cp[ra];
+  return true;
+}
+
+// NodeJoin split maps for colours k, output rank ro (dst slots C(k-2, ro)) and
+// nt rank rA (nt slots C(k-1, rA), a slots C(k-2, ro-rA)): per output slot c
+// and split j, xi[c][j] (bytes; the map's first words) then yi[cu'][c][j]
+// (16-bit), as nj_slot_map reads them.  Built with the slot maps above.
+constexpr size_t NJMAP_MAX = 16384, NJMAP_LDS_MAX = 32768;
+namespace {
+struct NjMaps {
+  uint32_t *d[12][12] = {};
+  int words[12][12] = {}, ns[12][12] = {};
+};
+std::map<std::pair<int, int>, NjMaps> njm;  // guarded by ejm_mu
+}  // namespace
+
+static bool njmaps_build(int dev, int k) {  // ejm_mu held
+  if (njm.count({dev, k})) return true;
+  NjMaps M;
+  for (int ro = 1; ro <= k - 2; ro++)
+    for (int rA = 1; rA <= ro; rA++) {
+      const int C = host_binom(k - 2, ro), ns = host_binom(ro, rA);
+      const size_t xb = ((size_t)C * ns + 3) & ~(size_t)3, yb = (size_t)(k - 1) * C * ns * 2;
+      if (xb + yb > NJMAP_MAX || host_binom(k - 2, ro - rA) > 255 || host_binom(k - 1, rA) > 65535) continue;
+      std::vector<uint32_t> uo(C);
+      for (uint32_t m = 0; m < (1u << (k - 2)); m++)
+        if (__builtin_popcount(m) == ro) uo[host_rank(m)] = m;
+      std::vector<uint8_t> h(xb + yb, 0);
+      uint16_t *yi = (uint16_t *)(h.data() + xb);
+      for (int c = 0; c < C; c++) {
+        int j = 0;
+        for (uint32_t S = uo[c];; S = (S - 1) & uo[c]) {  // subsets of uo[c] of size rA, in a fixed order
+          if (__builtin_popcount(S) == rA) {
+            h[(size_t)c * ns + j] = (uint8_t)host_rank(uo[c] & ~S);
+            for (int cu = 0; cu < k - 1; cu++) {
+              const uint32_t Sp = (S & ((1u << cu) - 1u)) | ((S >> cu) << (cu + 1));  // zero inserted at cu
+              yi[((size_t)cu * C + c) * ns + j] = (uint16_t)host_rank(Sp);
+            }
+            j++;
+          }
+          if (S == 0) break;
+        }
+      }
+      uint32_t *d = nullptr;
+      if (hipMalloc(&d, h.size()) != hipSuccess) return false;
+      if (hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) return false;
+      M.d[ro][rA] = d;
+      M.words[ro][rA] = (int)(h.size() / 4);
+      M.ns[ro][rA] = ns;
+    }
+  njm[{dev, k}] = M;
+  return true;
+}
+
+static bool njmap_find(int k, int ro, int rA, int C, int Ca, int Cn, const uint32_t **p, int *words, int *ns) {
+  if (ro < 1 || ro > 11 || rA < 1 || rA > ro || k < 3 || k > 12) return false;
+  if (C != host_binom(k - 2, ro) || Ca != host_binom(k - 2, ro - rA) || Cn != host_binom(k - 1, rA)) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(ejm_mu);
+  auto it = njm.find({dev, k});
+  if (it == njm.end() || !it->second.d[ro][rA]) return false;
+  *p = it->second.d[ro][rA];
+  *words = it->second.words[ro][rA];
+  *ns = it->second.ns[ro][rA];
   return true;
 }
 
@@ -1586,18 +1712,29 @@ void launch_axpyn(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev 
                   const TabDev *nt, const uint64_t *w, int nterms, RegDev dst, uint32_t *ovf, hipStream_t st) {
   AxpyTerms tm{};
   tm.n = nterms;
+  size_t lds = 0;
+  const bool maps = !getenv_flag_off("CC_NJMAP");
   for (int q = 0; q < nterms; q++) {
     tm.a[q] = a[q];
     tm.w[q] = w[q];
     tm.nt[q] = nt ? nt[q] : TabDev{nullptr, 0, 0};
+    tm.jm[q] = nullptr;
+    tm.jmw[q] = tm.jns[q] = 0;
+    if (maps && tm.nt[q].val &&
+        njmap_find(grp.k, dst.s - 2, tm.nt[q].s - 1, dst.C, a[q].C, tm.nt[q].C, &tm.jm[q], &tm.jmw[q], &tm.jns[q]))
+      lds += (size_t)tm.jmw[q] * 4;
+  }
+  if (lds > NJMAP_LDS_MAX) {  // keep the LDS of one launch modest: no maps
+    lds = 0;
+    for (int q = 0; q < nterms; q++) tm.jm[q] = nullptr, tm.jmw[q] = tm.jns[q] = 0;
   }
   if (grp.dense) {  // the activity word of dst is written by the same pass
     const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
-    hipLaunchKernelGGL(k_axpyn_dense, dim3(gr), dim3(BLK), 0, st, grp, n, colr, tm, dst, ovf, cur_lut());
+    hipLaunchKernelGGL(k_axpyn_dense, dim3(gr), dim3(BLK), lds, st, grp, n, colr, tm, dst, ovf, cur_lut());
     return;
   }
-  hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), 0, st, grp, n, colr, L, tm, dst, ovf,
-                     cur_lut());
+  hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), lds, st, grp, n, colr, L, tm, dst,
+                     ovf, cur_lut());
 }
 void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
   if (n <= 0) return;

@@ -44,8 +44,8 @@ PATH_MODES = {
     "light-large": {"CC_DENSE": "none", "CC_LIGHT_SCRATCH": "6000", "CC_LIGHT_LARGE": "1"},
     "fused-dense": {"CC_DENSE": "all", "CC_FUSE": "1"},
     "fused-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_FUSE": "1"},
-    "nomap-dense": {"CC_DENSE": "all", "CC_EJMAP": "0"},
-    "nomap-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJMAP": "0"},
+    "nomap-dense": {"CC_DENSE": "all", "CC_EJMAP": "0", "CC_NJMAP": "0"},
+    "nomap-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJMAP": "0", "CC_NJMAP": "0"},
 }
 
 
