@@ -1189,6 +1189,7 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
   for (int c = threadIdx.x; c < Ca; c += BLK) s_yi[c] = lut[LUT_RANK + (Kp & ~unrank(lut, a.s - 2, c))];
   __syncthreads();
   const int64_t N = nentries(grp, La);
+  uint64_t tlo = 0, thi = 0;
   for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < N; e += (int64_t)gridDim.x * BLK) {
     int64_t v;
     int b;
@@ -1204,29 +1205,42 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
       const uint64_t *br = bb.val + (eb * T + t) * Cb;
       uint64_t lo = 0, hi = 0;
       bool of = false;
-      for (int c = 0; c < Ca; c++) {
-        const uint64_t x = ar[c];
-        if (!x) continue;
-        const uint64_t y = br[s_yi[c]];
-        if (!y) continue;
-        uint64_t pl = x * y, ph = __umul64hi(x, y);
-        if (w != 1) {
-          const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
-          const uint64_t h2 = ph * w + c2;
-          if (__umul64hi(ph, w) != 0 || h2 < c2) of = true;
-          pl = l2;
-          ph = h2;
+      for (int c0 = 0; c0 < Ca; c0 += 4) {  // both rows' slots loaded before they are used
+        uint64_t xs[4], ys[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) xs[q] = c0 + q < Ca ? ar[c0 + q] : 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) ys[q] = c0 + q < Ca ? br[s_yi[c0 + q]] : 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const uint64_t x = xs[q], y = ys[q];
+          if (!x || !y) continue;
+          uint64_t pl = x * y, ph = __umul64hi(x, y);
+          if (w != 1) {
+            const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
+            const uint64_t h2 = ph * w + c2;
+            if (__umul64hi(ph, w) != 0 || h2 < c2) of = true;
+            pl = l2;
+            ph = h2;
+          }
+          const uint64_t sl = lo + pl;
+          hi += ph + (sl < pl ? 1u : 0u);
+          lo = sl;
         }
-        const uint64_t sl = lo + pl;
-        hi += ph + (sl < pl ? 1u : 0u);
-        lo = sl;
       }
       if (of) atomicOr(&acc.ovf[t], 1u);
       if (!(lo | hi)) continue;
       if (acc.per_src) atomic_add128(&acc.per_src[2 * (u * T + t)], lo, hi);
-      atomic_add128(&s_acc[2 * t], lo, hi);
+      if (T == 1) {  // one trial: the thread keeps its sum until the end
+        const uint64_t sl = tlo + lo;
+        thi += hi + (sl < lo ? 1u : 0u);
+        tlo = sl;
+      } else {
+        atomic_add128(&s_acc[2 * t], lo, hi);
+      }
     }
   }
+  if (tlo | thi) atomic_add128(&s_acc[0], tlo, thi);
   __syncthreads();
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (s_acc[2 * t] | s_acc[2 * t + 1]) atomic_add128(&acc.sum[2 * t], s_acc[2 * t], s_acc[2 * t + 1]);
