@@ -510,6 +510,9 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
     const int w = (int)wl;
     // output rows at w: dense -- every source above w; sparse -- the marks
     uint64_t ob = 0;
+    // w's edge range is loaded with its marks, not after them (one step less
+    // on the chain of dependent loads)
+    const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
     if (grp.dense) {
       for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_src[i + gl] > w) << i;
     } else {
@@ -521,7 +524,6 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           if (epi.regs[j].write) epi.regs[j].r.mask[w] = 0;
       continue;
     }
-    const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
     if (grp.dense && gl == 0)
       for (int j = 0; j < epi.nregs; j++) s_live[j * (NB / SW) + tid / SW] = 0;
     uint64_t rest = ob;
