@@ -241,6 +241,9 @@ constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps
 #ifndef EJ_MINW_DENSE
 #define EJ_MINW_DENSE 5
 #endif
+#ifndef EJ_UNROLL_S
+#define EJ_UNROLL_S 8  // slots of a row loaded before they are added (one-neighbour steps)
+#endif
 #ifndef EJ_UNROLL
 #define EJ_UNROLL 4  // slots of both rows loaded before they are added (two-neighbour steps)
 #endif
@@ -589,16 +592,15 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
             const uint64_t *rowA =
                 a.val + ((grp.dense ? (int64_t)vA * B + b : bA + __popcll(mfA & ((1ull << b) - 1ull))) * T + lt) * Ca;
             const uint32_t *mA = s_map + ((cu * grp.k + cA) * grp.k + cw) * (emap_cp >> 2);
-            for (int c0 = 0; c0 < Ca; c0 += 4) {
-              uint64_t xa[4];
+            for (int c0 = 0; c0 < Ca; c0 += EJ_UNROLL_S) {
+              uint64_t xa[EJ_UNROLL_S];
 #pragma unroll
-              for (int q = 0; q < 4; q++) xa[q] = c0 + q < Ca ? rowA[c0 + q] : 0;
-              const uint32_t mw = MAP ? mA[c0 >> 2] : 0;
+              for (int q = 0; q < EJ_UNROLL_S; q++) xa[q] = c0 + q < Ca ? rowA[c0 + q] : 0;
 #pragma unroll
-              for (int q = 0; q < 4; q++) {
+              for (int q = 0; q < EJ_UNROLL_S; q++) {
                 if (!xa[q]) continue;
                 if (MAP) {
-                  const uint32_t o = (mw >> (8 * q)) & 0xffu;
+                  const uint32_t o = (mA[(c0 + q) >> 2] >> (8 * (q & 3))) & 0xffu;
                   if (o != 0xffu) add_ck(acc[o * NB + tid], xa[q], of);
                 } else {
                   const uint32_t R = spread2(s_um[c0 + q], cu, cA);
