@@ -647,12 +647,12 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
                 xa[q] = okA && c0 + q < Ca ? rowA[c0 + q] : 0;
                 xb[q] = okB && c0 + q < Ca ? rowB[c0 + q] : 0;
               }
-              static_assert(!MAP || EJ_UNROLL == 4, "map words hold four slots");
-              const uint32_t mwA = MAP ? mA[c0 >> 2] : 0, mwB = MAP ? mB[c0 >> 2] : 0;
+              static_assert(EJ_UNROLL % 4 == 0, "map words hold four slots");
 #pragma unroll
               for (int q = 0; q < EJ_UNROLL; q++) {
                 if (MAP) {
-                  const uint32_t oA = (mwA >> (8 * q)) & 0xffu, oB = (mwB >> (8 * q)) & 0xffu;
+                  const uint32_t oA = (mA[(c0 + q) >> 2] >> (8 * (q & 3))) & 0xffu;
+                  const uint32_t oB = (mB[(c0 + q) >> 2] >> (8 * (q & 3))) & 0xffu;
                   if (xa[q] && oA != 0xffu) add_ck(acc[oA * NB + tid], xa[q], of);
                   if (xb[q] && oB != 0xffu) add_ck(acc[oB * NB + tid], xb[q], of);
                   continue;
