@@ -461,7 +461,13 @@ constexpr size_t EJV_LDS_MAX = 56 * 1024;
 // source's colour cu, the neighbour's colour cv and the output vertex's colour
 // cw give the output slot, or none when cw is already used) is read from a
 // table [cu][cv][cw][c] of bytes (0xff: none), four slots per LDS word.
-template <bool ANN, int SW, bool EPI, int NB, bool MAP>
+//
+// With PACK (one trial, whole wavefronts, slot maps, no epilogue) the lanes do
+// not each wait for their own source's rows: the (neighbour, source) pairs of
+// a step of 64 neighbours that relax a row are numbered by an exclusive scan
+// of their counts, and each lane takes one pair a round, adding into the
+// source's column with LDS atomics (checked through the returned old value).
+template <bool ANN, int SW, bool EPI, int NB, bool MAP, bool PACK = false>
 __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_MINW_DENSE) : 1) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                                               const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
                                               AccDev accd, const uint16_t *lut, const uint32_t *emap, int emap_w,
@@ -494,6 +500,17 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
   uint32_t *const s_map = (uint32_t *)((char *)accs + ejv_lds(epi.ncols, epi.nregs, EPI, NB));
   if (MAP)
     for (int i = tid; i < emap_w; i += NB) s_map[i] = emap[i];
+  __shared__ uint64_t s_cm[16];  // PACK: the sources of each colour (bit b: source b)
+  __shared__ uint8_t s_cu[WAVE];  // PACK: source b's colour
+  if (PACK) {
+    if (tid < 16) s_cm[tid] = 0;
+    __syncthreads();
+    if (tid < B) {
+      const int c = colr[grp.src[tid]];
+      s_cu[tid] = (uint8_t)c;
+      atomicOr((unsigned long long *)&s_cm[c], 1ull << tid);
+    }
+  }
   __syncthreads();
   constexpr int NG = WAVE / SW;  // groups per wavefront
   const int gl = lane % SW, gbase = lane - gl;
@@ -573,7 +590,47 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
         const bool stop = gballot(vj == VNONE) != 0;
         // one trial: the neighbour's colour travels with it (loaded by its own lane)
         const int cvj = (T == 1 && inb) ? colr[vj] : 0;
-        if (!ANN && SW < 64) {
+        if (PACK) {
+          // sources that relax a row from neighbour j: bit set in inb, colour
+          // neither the neighbour's nor w's (w's colour: the source is idle at w)
+          const int cwv = colr[w];
+          const uint64_t valid = (inb && cvj != cwv) ? inb & ~s_cm[cvj] & ~s_cm[cwv] : 0ull;
+          int incl = __popcll(valid);
+          for (int o = 1; o < WAVE; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+          }
+          const int excl = incl - __popcll(valid), P = __shfl(incl, WAVE - 1);
+          for (int p0 = 0; p0 < P; p0 += WAVE) {
+            const int pp = p0 + lane;
+            int jl = 0;  // the last neighbour whose first pair is at or before pp
+            for (int st = 32; st > 0; st >>= 1)
+              if (__shfl(excl, jl + st) <= pp) jl += st;
+            const int kth = pp - __shfl(excl, jl);
+            const int vA = __shfl(vj, jl), cA = __shfl(cvj, jl);
+            const uint64_t vm = __shfl(valid, jl);
+            if (pp >= P) continue;
+            const int bb = nth_set_bit(vm, kth);
+            if (vA >= s_src[bb]) continue;
+            n_rows++;
+            const int colw = (tid - lane) + __popcll(pass & ((1ull << bb) - 1ull));  // the lane of source bb
+            const uint64_t *row = a.val + ((int64_t)vA * B + bb) * Ca;
+            const uint32_t *mA = s_map + ((s_cu[bb] * grp.k + cA) * grp.k + cwv) * (emap_cp >> 2);
+            for (int c0 = 0; c0 < Ca; c0 += 4) {
+              uint64_t xa[4];
+#pragma unroll
+              for (int q = 0; q < 4; q++) xa[q] = c0 + q < Ca ? row[c0 + q] : 0;
+#pragma unroll
+              for (int q = 0; q < 4; q++) {
+                if (!xa[q]) continue;
+                const uint32_t o = (mA[(c0 + q) >> 2] >> (8 * (q & 3))) & 0xffu;
+                if (o == 0xffu) continue;
+                const uint64_t old = atomicAdd((unsigned long long *)&accs[o * NB + colw], (unsigned long long)xa[q]);
+                of |= old + xa[q] < old;
+              }
+            }
+          }
+        } else if (!ANN && SW < 64) {
           // quarter wavefronts: one neighbour per step, few registers (more
           // wavefronts in flight hide the per-vertex load chains)
           while (todo) {
@@ -709,6 +766,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
         }
         if (stop) break;
       }
+      if (PACK) __threadfence_block();  // other lanes' LDS atomics into this lane's column are done
       // epilogue: row-local ops on the rows of w, operands in LDS or read
       // from global memory at their own level
       if (EPI && b >= 0 && epi.nops) {
@@ -1666,6 +1724,8 @@ void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, 
                      etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp)
 #define CC_EJV2(ANN_, SW_, EPI_, MAP_) \
   if (wide) CC_EJV(ANN_, SW_, EPI_, EJ_BLK, MAP_); else CC_EJV(ANN_, SW_, EPI_, WAVE, MAP_)
+  // one trial in dense groups: (neighbour, source) pairs packed over the lanes
+  const bool pack = grp.dense && grp.T == 1 && grp.k <= 16 && !getenv_flag_off("CC_EJPACK");
   const int sel = (mp ? 8 : 0) | (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
   switch (sel) {
     case 0: CC_EJV2(false, 64, false, false); break;
@@ -1676,7 +1736,18 @@ void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, 
     case 5: CC_EJV2(true, 64, true, false); break;
     case 6: CC_EJV2(true, 16, false, false); break;
     case 7: CC_EJV2(true, 16, true, false); break;
-    case 8: CC_EJV2(false, 64, false, true); break;
+    case 8:
+      if (pack) {
+        if (wide)
+          hipLaunchKernelGGL((k_ejv<false, 64, false, EJ_BLK, true, true>), dim3(gr), dim3(EJ_BLK), lds, st, g, grp,
+                             colr, Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
+        else
+          hipLaunchKernelGGL((k_ejv<false, 64, false, WAVE, true, true>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr,
+                             Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
+      } else {
+        CC_EJV2(false, 64, false, true);
+      }
+      break;
     case 9: CC_EJV2(false, 64, true, true); break;
     case 10: CC_EJV2(false, 16, false, true); break;
     default: CC_EJV2(false, 16, true, true); break;

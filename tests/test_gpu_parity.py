@@ -85,6 +85,27 @@ def test_small_shapes_match_oracle(small_graphs, name, dense_mode):
             assert int(counts[t]) == want
 
 
+@pytest.mark.parametrize("mode", ["dense", "dense-unpacked"])
+@pytest.mark.parametrize("name", sorted(SHAPES))
+def test_one_trial_dense(small_graphs, name, mode, monkeypatch):
+    """One colouring per solve in dense groups: the EdgeJoin packs (neighbour,
+    source) pairs over the lanes (dense-unpacked: one source per lane)."""
+    monkeypatch.setenv("CC_DENSE", "all")
+    if mode == "dense-unpacked":
+        monkeypatch.setenv("CC_EJPACK", "0")
+    k, E = SHAPES[name]
+    q = cc.Query(k, E)
+    for gi, g in enumerate(small_graphs):
+        print(f"[parity] {name} graph{gi} n={g.n} m={g.m} mode={mode} T=1", flush=True)
+        dg = cc.Graph.from_csr(g)
+        col = _colours(g.n, k, 2, seed=200 + gi)
+        for t in range(2):
+            counts, ovf, exact = cc.count_colors(dg, q, col[t:t + 1])
+            want = O.db(g, k, E, col[t])
+            assert not ovf[0]
+            assert exact[0] == want and int(counts[0]) == want, (name, gi, t, exact[0], want)
+
+
 def test_colour_contract_device_equals_oracle():
     g = graphs.erdos_renyi(500, 6.0, seed=5)
     dg = cc.Graph.from_csr(g)
