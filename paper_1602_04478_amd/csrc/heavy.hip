@@ -241,6 +241,9 @@ constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps
 #ifndef EJ_MINW_DENSE
 #define EJ_MINW_DENSE 5
 #endif
+#ifndef EJ_UNROLL_P
+#define EJ_UNROLL_P 8  // slots of a row loaded before they are added (pairs packed over the lanes)
+#endif
 #ifndef EJ_UNROLL_S
 #define EJ_UNROLL_S 8  // slots of a row loaded before they are added (one-neighbour steps)
 #endif
@@ -462,9 +465,9 @@ constexpr size_t EJV_LDS_MAX = 56 * 1024;
 // cw give the output slot, or none when cw is already used) is read from a
 // table [cu][cv][cw][c] of bytes (0xff: none), four slots per LDS word.
 //
-// With PACK (one trial, whole wavefronts, slot maps, no epilogue) the lanes do
+// With PACK (one trial, slot maps, no epilogue) the lanes of a group do
 // not each wait for their own source's rows: the (neighbour, source) pairs of
-// a step of 64 neighbours that relax a row are numbered by an exclusive scan
+// a step of SW neighbours that relax a row are numbered by an exclusive scan
 // of their counts, and each lane takes one pair a round, adding into the
 // source's column with LDS atomics (checked through the returned old value).
 template <bool ANN, int SW, bool EPI, int NB, bool MAP, bool PACK = false>
@@ -596,32 +599,37 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
           const int cwv = colr[w];
           const uint64_t valid = (inb && cvj != cwv) ? inb & ~s_cm[cvj] & ~s_cm[cwv] : 0ull;
           int incl = __popcll(valid);
-          for (int o = 1; o < WAVE; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
+          for (int o = 1; o < SW; o <<= 1) {
+            const int y = __shfl_up(incl, o, SW);
+            if (gl >= o) incl += y;
           }
-          const int excl = incl - __popcll(valid), P = __shfl(incl, WAVE - 1);
-          for (int p0 = 0; p0 < P; p0 += WAVE) {
-            const int pp = p0 + lane;
+          const int excl = incl - __popcll(valid), P = __shfl(incl, SW - 1, SW);
+          for (int p0 = 0; p0 < P; p0 += SW) {
+            const int pp = p0 + gl;
             int jl = 0;  // the last neighbour whose first pair is at or before pp
-            for (int st = 32; st > 0; st >>= 1)
-              if (__shfl(excl, jl + st) <= pp) jl += st;
-            const int kth = pp - __shfl(excl, jl);
-            const int vA = __shfl(vj, jl), cA = __shfl(cvj, jl);
-            const uint64_t vm = __shfl(valid, jl);
+            for (int st = SW / 2; st > 0; st >>= 1)
+              if (__shfl(excl, jl + st, SW) <= pp) jl += st;
+            const int kth = pp - __shfl(excl, jl, SW);
+            const int vA = __shfl(vj, jl, SW), cA = __shfl(cvj, jl, SW);
+            const uint64_t vm = __shfl(valid, jl, SW);
+            // (packed launches: whole wavefronts for dense groups, quarters for sparse ones)
+            constexpr bool PD = SW == WAVE;
+            const uint64_t mfA = PD ? 0 : __shfl(mfull, jl, SW);
+            const int64_t bA = PD ? 0 : __shfl(bj, jl, SW);
             if (pp >= P) continue;
             const int bb = nth_set_bit(vm, kth);
             if (vA >= s_src[bb]) continue;
             n_rows++;
-            const int colw = (tid - lane) + __popcll(pass & ((1ull << bb) - 1ull));  // the lane of source bb
-            const uint64_t *row = a.val + ((int64_t)vA * B + bb) * Ca;
+            const uint64_t below_bb = (1ull << bb) - 1ull;
+            const int colw = (tid - gl) + __popcll(pass & below_bb);  // the lane of source bb
+            const uint64_t *row = a.val + (PD ? (int64_t)vA * B + bb : bA + __popcll(mfA & below_bb)) * Ca;
             const uint32_t *mA = s_map + ((s_cu[bb] * grp.k + cA) * grp.k + cwv) * (emap_cp >> 2);
-            for (int c0 = 0; c0 < Ca; c0 += 4) {
-              uint64_t xa[4];
+            for (int c0 = 0; c0 < Ca; c0 += EJ_UNROLL_P) {
+              uint64_t xa[EJ_UNROLL_P];
 #pragma unroll
-              for (int q = 0; q < 4; q++) xa[q] = c0 + q < Ca ? row[c0 + q] : 0;
+              for (int q = 0; q < EJ_UNROLL_P; q++) xa[q] = c0 + q < Ca ? row[c0 + q] : 0;
 #pragma unroll
-              for (int q = 0; q < 4; q++) {
+              for (int q = 0; q < EJ_UNROLL_P; q++) {
                 if (!xa[q]) continue;
                 const uint32_t o = (mA[(c0 + q) >> 2] >> (8 * (q & 3))) & 0xffu;
                 if (o == 0xffu) continue;
@@ -1724,8 +1732,8 @@ void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, 
                      etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp)
 #define CC_EJV2(ANN_, SW_, EPI_, MAP_) \
   if (wide) CC_EJV(ANN_, SW_, EPI_, EJ_BLK, MAP_); else CC_EJV(ANN_, SW_, EPI_, WAVE, MAP_)
-  // one trial in dense groups: (neighbour, source) pairs packed over the lanes
-  const bool pack = grp.dense && grp.T == 1 && grp.k <= 16 && !getenv_flag_off("CC_EJPACK");
+  // one trial: (neighbour, source) pairs packed over the lanes
+  const bool pack = grp.T == 1 && grp.k <= 16 && !getenv_flag_off("CC_EJPACK");
   const int sel = (mp ? 8 : 0) | (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
   switch (sel) {
     case 0: CC_EJV2(false, 64, false, false); break;
@@ -1749,7 +1757,18 @@ void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, 
       }
       break;
     case 9: CC_EJV2(false, 64, true, true); break;
-    case 10: CC_EJV2(false, 16, false, true); break;
+    case 10:
+      if (pack) {
+        if (wide)
+          hipLaunchKernelGGL((k_ejv<false, 16, false, EJ_BLK, true, true>), dim3(gr), dim3(EJ_BLK), lds, st, g, grp,
+                             colr, Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
+        else
+          hipLaunchKernelGGL((k_ejv<false, 16, false, WAVE, true, true>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr,
+                             Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
+      } else {
+        CC_EJV2(false, 16, false, true);
+      }
+      break;
     default: CC_EJV2(false, 16, true, true); break;
   }
 #undef CC_EJV2

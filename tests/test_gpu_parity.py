@@ -85,14 +85,21 @@ def test_small_shapes_match_oracle(small_graphs, name, dense_mode):
             assert int(counts[t]) == want
 
 
-@pytest.mark.parametrize("mode", ["dense", "dense-unpacked"])
+ONE_TRIAL_MODES = {
+    "dense": {"CC_DENSE": "all"},
+    "dense-unpacked": {"CC_DENSE": "all", "CC_EJPACK": "0"},
+    "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
+    "sparse-unpacked": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJPACK": "0"},
+}
+
+
+@pytest.mark.parametrize("mode", sorted(ONE_TRIAL_MODES))
 @pytest.mark.parametrize("name", sorted(SHAPES))
-def test_one_trial_dense(small_graphs, name, mode, monkeypatch):
-    """One colouring per solve in dense groups: the EdgeJoin packs (neighbour,
-    source) pairs over the lanes (dense-unpacked: one source per lane)."""
-    monkeypatch.setenv("CC_DENSE", "all")
-    if mode == "dense-unpacked":
-        monkeypatch.setenv("CC_EJPACK", "0")
+def test_one_trial(small_graphs, name, mode, monkeypatch):
+    """One colouring per solve: the EdgeJoin packs (neighbour, source) pairs
+    over the lanes of a group (unpacked: one source per lane)."""
+    for key, val in ONE_TRIAL_MODES[mode].items():
+        monkeypatch.setenv(key, val)
     k, E = SHAPES[name]
     q = cc.Query(k, E)
     for gi, g in enumerate(small_graphs):
