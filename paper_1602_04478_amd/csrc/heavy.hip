@@ -241,6 +241,9 @@ constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps
 #ifndef EJ_MINW_DENSE
 #define EJ_MINW_DENSE 5
 #endif
+#ifndef EJ_PACK_SW
+#define EJ_PACK_SW 16  // lanes per output vertex in sparse groups with packed pairs
+#endif
 #ifndef EJ_UNROLL_P
 #define EJ_UNROLL_P 8  // slots of a row loaded before they are added (pairs packed over the lanes)
 #endif
@@ -1725,15 +1728,17 @@ void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, 
   const size_t lds = ejv_lds(epi.ncols, epi.nregs, ep, nb) + mapb;
   // sparse groups meet few sources per vertex: four vertices per wavefront
   const bool quarter = !grp.dense && grp.T <= 16;
-  const int64_t nw = quarter ? (grp.n_lim + 3) / 4 : grp.n_lim;  // wavefronts' worth of vertices
+  // one trial: (neighbour, source) pairs packed over the lanes
+  const bool pack = grp.T == 1 && grp.k <= 16 && !getenv_flag_off("CC_EJPACK");
+  const bool spk = quarter && pack && mp && !ep && !etab.val;  // sparse, packed: EJ_PACK_SW lanes per vertex
+  const int vpw = spk ? WAVE / EJ_PACK_SW : quarter ? 4 : 1;  // vertices per wavefront
+  const int64_t nw = (grp.n_lim + vpw - 1) / vpw;  // wavefronts' worth of vertices
   const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((nw + nb / WAVE - 1) / (nb / WAVE), 32768 / (nb / WAVE)));
 #define CC_EJV(ANN_, SW_, EPI_, NB_, MAP_)                                                                   \
   hipLaunchKernelGGL((k_ejv<ANN_, SW_, EPI_, NB_, MAP_>), dim3(gr), dim3(NB_), lds, st, g, grp, colr, Lin, a, epi, \
                      etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp)
 #define CC_EJV2(ANN_, SW_, EPI_, MAP_) \
   if (wide) CC_EJV(ANN_, SW_, EPI_, EJ_BLK, MAP_); else CC_EJV(ANN_, SW_, EPI_, WAVE, MAP_)
-  // one trial: (neighbour, source) pairs packed over the lanes
-  const bool pack = grp.T == 1 && grp.k <= 16 && !getenv_flag_off("CC_EJPACK");
   const int sel = (mp ? 8 : 0) | (etab.val ? 4 : 0) | (quarter ? 2 : 0) | (ep ? 1 : 0);
   switch (sel) {
     case 0: CC_EJV2(false, 64, false, false); break;
@@ -1760,11 +1765,11 @@ void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, 
     case 10:
       if (pack) {
         if (wide)
-          hipLaunchKernelGGL((k_ejv<false, 16, false, EJ_BLK, true, true>), dim3(gr), dim3(EJ_BLK), lds, st, g, grp,
-                             colr, Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
+          hipLaunchKernelGGL((k_ejv<false, EJ_PACK_SW, false, EJ_BLK, true, true>), dim3(gr), dim3(EJ_BLK), lds, st, g,
+                             grp, colr, Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
         else
-          hipLaunchKernelGGL((k_ejv<false, 16, false, WAVE, true, true>), dim3(gr), dim3(WAVE), lds, st, g, grp, colr,
-                             Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
+          hipLaunchKernelGGL((k_ejv<false, EJ_PACK_SW, false, WAVE, true, true>), dim3(gr), dim3(WAVE), lds, st, g, grp,
+                             colr, Lin, a, epi, etab, e_src_first, ovf, acc, cur_lut(), em, emw, emcp);
       } else {
         CC_EJV2(false, 16, false, true);
       }
