@@ -186,8 +186,9 @@ cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint6
 /*
  * What the calling thread's last cc_count_batch chose for its last query
  * (online tuning when `tuning` was NULL): the dense cut (the model's, half and
- * double, one colouring per group) and then the trial-group size, the
- * candidates timed and their seconds per colouring, and the graph replays.
+ * double, one colouring per group) and then the trial-group size (not tried
+ * when one colouring takes 0.25 s or more), the candidates timed and their
+ * seconds per colouring, and the graph replays.
  */
 typedef struct {
   int32_t trial_group;

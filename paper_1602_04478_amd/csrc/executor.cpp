@@ -1442,8 +1442,12 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
       if (!trial(1, d)) break;
     }
   }
-  // 2. the trial-group size at that cut: 2, 4, ... while it keeps improving
-  for (int cand = 2; cand <= 64 && t0 + 2 * cand <= trials; cand *= 2) {
+  // 2. the trial-group size at that cut: 2, 4, ... while it keeps improving.
+  // Skipped when one colouring already takes long (kTrialGroupMaxSec): its
+  // work then outweighs its launch sequence, and groups of one colouring keep
+  // the packed EdgeJoin (one trial only).
+  constexpr double kTrialGroupMaxSec = 0.25;
+  for (int cand = 2; cand <= 64 && t0 + 2 * cand <= trials && best_per < kTrialGroupMaxSec; cand *= 2) {
     const double before = best_per;
     if (!trial(cand, best_dense)) break;
     if (best_per >= before) break;
