@@ -247,6 +247,12 @@ constexpr int VMAX_C = 96;  // slots up to which the vertex-major EdgeJoin keeps
 #ifndef EJ_UNROLL_P
 #define EJ_UNROLL_P 8  // slots of a row loaded before they are added (pairs packed over the lanes)
 #endif
+#ifndef EJ_UNROLL_PD
+#define EJ_UNROLL_PD 12  // the same in dense groups, at four wavefronts per SIMD (EJ_MINW_PD)
+#endif
+#ifndef EJ_MINW_PD
+#define EJ_MINW_PD 4
+#endif
 #ifndef EJ_UNROLL_S
 #define EJ_UNROLL_S 8  // slots of a row loaded before they are added (one-neighbour steps)
 #endif
@@ -474,7 +480,7 @@ constexpr size_t EJV_LDS_MAX = 56 * 1024;
 // of their counts, and each lane takes one pair a round, adding into the
 // source's column with LDS atomics (checked through the returned old value).
 template <bool ANN, int SW, bool EPI, int NB, bool MAP, bool PACK = false>
-__global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_MINW_DENSE) : 1) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
+__global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK ? EJ_MINW_PD : EJ_MINW_DENSE) : 1) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                                               const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
                                               AccDev accd, const uint16_t *lut, const uint32_t *emap, int emap_w,
                                               int emap_cp) {
@@ -627,12 +633,13 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : EJ_M
             const int colw = (tid - gl) + __popcll(pass & below_bb);  // the lane of source bb
             const uint64_t *row = a.val + (PD ? (int64_t)vA * B + bb : bA + __popcll(mfA & below_bb)) * Ca;
             const uint32_t *mA = s_map + ((s_cu[bb] * grp.k + cA) * grp.k + cwv) * (emap_cp >> 2);
-            for (int c0 = 0; c0 < Ca; c0 += EJ_UNROLL_P) {
-              uint64_t xa[EJ_UNROLL_P];
+            constexpr int UP = PD ? EJ_UNROLL_PD : EJ_UNROLL_P;
+            for (int c0 = 0; c0 < Ca; c0 += UP) {
+              uint64_t xa[UP];
 #pragma unroll
-              for (int q = 0; q < EJ_UNROLL_P; q++) xa[q] = c0 + q < Ca ? row[c0 + q] : 0;
+              for (int q = 0; q < UP; q++) xa[q] = c0 + q < Ca ? row[c0 + q] : 0;
 #pragma unroll
-              for (int q = 0; q < EJ_UNROLL_P; q++) {
+              for (int q = 0; q < UP; q++) {
                 if (!xa[q]) continue;
                 const uint32_t o = (mA[(c0 + q) >> 2] >> (8 * (q & 3))) & 0xffu;
                 if (o == 0xffu) continue;
