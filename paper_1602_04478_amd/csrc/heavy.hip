@@ -916,6 +916,17 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
   }
 }
 
+// The group's source ranks and their colours per trial in LDS, for kernels
+// that need them per slot: one LDS read instead of two dependent global loads.
+__device__ __forceinline__ void load_sources(const GroupDev &grp, const uint8_t *colr, int64_t n, int32_t *s_u,
+                                             uint8_t *s_cu) {
+  for (int i = threadIdx.x; i < WAVE; i += blockDim.x) s_u[i] = i < grp.B ? grp.src[i] : 0;
+  for (int i = threadIdx.x; i < grp.T * WAVE; i += blockDim.x) {
+    const int t = i / WAVE, b = i - t * WAVE;
+    s_cu[i] = b < grp.B ? colr[(int64_t)t * n + grp.src[b]] : 0;
+  }
+}
+
 // ------------------------------------------------------------------ NodeJoin
 // dst[(v,b)][R'] = sum over splits R' = R + Ra of a[(v,b)][R] * A[v][Ra]
 __global__ __launch_bounds__(BLK) void k_nj(GroupDev grp, int64_t n, const uint8_t *colr, LevelDev L, RegDev a,
@@ -1056,6 +1067,9 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_uo[256];  // unranked slots of dst
   extern __shared__ uint32_t s_jm[];
+  __shared__ int32_t s_u[WAVE];
+  __shared__ uint8_t s_cu[WAVE * WAVE];
+  load_sources(grp, colr, n, s_u, s_cu);
   load_jmaps(tm, s_jm);
   load_rank(s_rank, lut);
   const int T = grp.T, C = dst.C;
@@ -1076,8 +1090,8 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
         int64_t v;
         int b;
         entry_vb(grp, L, row, v, b);
-        const int64_t u = grp.src[b];
-        const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+        const int64_t u = s_u[b];
+        const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
         x = 0;
         if (v < u && cu != cv) {
           if (tm.jmw[q]) {
@@ -1193,6 +1207,9 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_uo[256];  // unranked slots of dst
   extern __shared__ uint32_t s_jm[];
+  __shared__ int32_t s_u[WAVE];
+  __shared__ uint8_t s_cu[WAVE * WAVE];
+  load_sources(grp, colr, n, s_u, s_cu);
   load_jmaps(tm, s_jm);
   load_rank(s_rank, lut);
   const int T = grp.T, C = dst.C, B = grp.B;
@@ -1226,8 +1243,8 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
         if (q >= tm.n || !((mt[q] >> b) & 1ull)) continue;
         uint64_t x;
         if (tm.nt[q].val) {
-          const int64_t u = grp.src[b];
-          const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+          const int64_t u = s_u[b];
+          const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
           x = 0;
           if (v < u && cu != cv) {
             if (tm.jmw[q]) {
@@ -1263,6 +1280,9 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
   // colour set in k - 2 bits.
   __shared__ uint16_t s_yi[256];  // b's slot partnering a's slot c
   __shared__ uint64_t s_acc[2 * 64];
+  __shared__ int32_t s_u[WAVE];
+  __shared__ uint8_t s_cu[WAVE * WAVE];
+  load_sources(grp, colr, n, s_u, s_cu);
   for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) s_acc[i] = 0;
   const int T = grp.T, Ca = a.C, Cb = bb.C, k = grp.k;
   const uint32_t Kp = (1u << (k - 2)) - 1u;
@@ -1277,9 +1297,9 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
     if (!live(grp, a, v, b)) continue;
     const int64_t eb = row_of(grp, Lb, bb, v, b);
     if (eb < 0) continue;
-    const int64_t u = grp.src[b];
+    const int64_t u = s_u[b];
     for (int t = 0; t < T; t++) {
-      const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+      const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
       if (cu == cv) continue;
       const uint64_t *ar = a.val + (e * T + t) * Ca;
       const uint64_t *br = bb.val + (eb * T + t) * Cb;
