@@ -1079,10 +1079,10 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
     switch (op.kind) {
       case OP_INIT: {
         RegDev d = regdev(op.dst);
-        if (G.dense) {
-          launch_fill_u64(d.val, grp.n_lim * grp.B * (int64_t)Tg * d.C, st);
-          launch_fill_u64(d.mask, grp.n_lim, st);
-        }
+        // dense: only the activity words are cleared; k_init writes every slot
+        // of the rows it marks, and every reader of a dense register reads a
+        // row only when its activity bit is set
+        if (G.dense) launch_fill_u64(d.mask, grp.n_lim, st);
         launch_init(gd_, grp, lowcnt_d, max_low, colr, lv(op.dst), d, tabdev(op.tab), op.tab_src_first,
                     tabdev(op.ntab), ovf, st);
         break;
