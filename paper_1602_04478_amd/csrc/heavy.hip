@@ -91,20 +91,37 @@ __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int
   }
 }
 
-// depth d+1 from depth d: every lower neighbour w < u_b of an entry (v, b)
+// depth d+1 from depth d: every lower neighbour w < u_b of an entry (v, b).
+// A team of lanes takes a vertex v with all its entries (the marks m of v):
+// neighbour w (ascending) gets the sources b of m with w < u_b in one atomic
+// OR; below the smallest such u_b that is all of m.
 __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lout) {
   constexpr int TEAM = 16;
+  __shared__ int32_t s_u[64];
+  for (int i = threadIdx.x; i < 64; i += BLK) s_u[i] = i < grp.B ? grp.src[i] : 0;
+  __syncthreads();
   const int teams = BLK / TEAM, team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
-  const int64_t N = *Lin.cnt;
-  for (int64_t e = (int64_t)blockIdx.x * teams + team; e < N; e += (int64_t)gridDim.x * teams) {
-    const int64_t x = Lin.list[e];
-    const int64_t v = x >> 6;
-    const int b = (int)(x & 63);
-    const int64_t u = grp.src[b];
+  for (int64_t v = (int64_t)blockIdx.x * teams + team; v < grp.n_lim; v += (int64_t)gridDim.x * teams) {
+    const uint64_t m = Lin.mb[2 * v];
+    if (!m) continue;
+    int umin = 0x7fffffff, umax = 0;
+    for (uint64_t r = m; r; r &= r - 1) {
+      const int u = s_u[__builtin_ctzll(r)];
+      umin = min(umin, u);
+      umax = max(umax, u);
+    }
     for (int64_t ee = g.rp[v] + lane; ee < g.rp[v + 1]; ee += TEAM) {
       const int64_t w = g.col[ee];
-      if (w >= u) break;
-      mark(Lout.mb, 2 * w, b);
+      if (w >= umax) break;
+      uint64_t mask = m;
+      if (w >= umin) {
+        mask = 0;
+        for (uint64_t r = m; r; r &= r - 1) {
+          const int b = __builtin_ctzll(r);
+          if (w < s_u[b]) mask |= 1ull << b;
+        }
+      }
+      if ((Lout.mb[2 * w] & mask) != mask) atomicOr((unsigned long long *)&Lout.mb[2 * w], (unsigned long long)mask);
     }
   }
 }
