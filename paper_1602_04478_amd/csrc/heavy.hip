@@ -126,20 +126,27 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
   }
 }
 
-// exclusive prefix sum over the workgroup; returns the total in *tot
+// exclusive prefix sum over the workgroup (BLK threads, all calling); the
+// total in tot.  Wavefront scans by shuffles, then the wavefronts' totals
+// through s (at least BLK / 64 words).
 __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t *s, uint32_t &tot) {
-  s[threadIdx.x] = x;
-  __syncthreads();
-  for (int o = 1; o < BLK; o <<= 1) {
-    const uint32_t y = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
-    __syncthreads();
-    s[threadIdx.x] += y;
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
   }
-  tot = s[BLK - 1];
-  const uint32_t r = s[threadIdx.x] - x;
+  if (lane == 63) s[wv] = inc;
   __syncthreads();
-  return r;
+  uint32_t base = 0, t = 0;
+  for (int i = 0; i < BLK / 64; i++) {
+    const uint32_t c = s[i];
+    base += i < wv ? c : 0u;
+    t += c;
+  }
+  tot = t;
+  __syncthreads();  // s is reused by the next call
+  return base + inc - x;
 }
 
 // marks per chunk (thread t reads vertices lo + i * BLK + t: coalesced)
