@@ -1254,6 +1254,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
       }
     if (lane == 0) dst.mask[v] = m;
     if (!m) continue;
+    const int cv1 = T == 1 ? colr[v] : 0;  // one trial: v's colour, loaded once for all its items
     const int items = __popcll(m) * per;
     for (int it = lane; it < items; it += 64) {
       const int q0 = it / per, r = it - q0 * per, t = r / C, c = r - t * C;
@@ -1268,7 +1269,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
         uint64_t x;
         if (tm.nt[q].val) {
           const int64_t u = s_u[b];
-          const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
+          const int cu = s_cu[t * WAVE + b], cv = T == 1 ? cv1 : colr[(int64_t)t * n + v];
           x = 0;
           if (v < u && cu != cv) {
             if (tm.jmw[q]) {
