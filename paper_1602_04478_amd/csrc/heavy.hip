@@ -1226,6 +1226,8 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
   flag_trials(ovf, ofm);
 }
 
+// JM: every NodeJoin term has a split map (the subset walk is not compiled in)
+template <bool JM>
 __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, const uint8_t *colr, AxpyTerms tm,
                                                      RegDev dst, uint32_t *ovf, const uint16_t *lut) {
   __shared__ uint16_t s_rank[2048];
@@ -1272,10 +1274,11 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
           const int cu = s_cu[t * WAVE + b], cv = T == 1 ? cv1 : colr[(int64_t)t * n + v];
           x = 0;
           if (v < u && cu != cv) {
-            if (tm.jmw[q]) {
+            if (JM || tm.jmw[q]) {
               const int ns = tm.jns[q];
               const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
-              const uint16_t *yi = (const uint16_t *)(jmap_at(tm, s_jm, q) + ((C * ns + 3) >> 2)) + ((cu - (cv < cu)) * C + c) * ns;
+              const uint16_t *yi =
+                  (const uint16_t *)(jmap_at(tm, s_jm, q) + ((C * ns + 3) >> 2)) + ((cu - (cv < cu)) * C + c) * ns;
               x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi,
                               yi, ns, of);
             } else {
@@ -1895,7 +1898,12 @@ void launch_axpyn(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev 
   }
   if (grp.dense) {  // the activity word of dst is written by the same pass
     const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
-    hipLaunchKernelGGL(k_axpyn_dense, dim3(gr), dim3(BLK), lds, st, grp, n, colr, tm, dst, ovf, cur_lut());
+    bool jm = true;
+    for (int q = 0; q < nterms; q++) jm = jm && (!tm.nt[q].val || tm.jmw[q]);
+    if (jm)
+      hipLaunchKernelGGL(k_axpyn_dense<true>, dim3(gr), dim3(BLK), lds, st, grp, n, colr, tm, dst, ovf, cur_lut());
+    else
+      hipLaunchKernelGGL(k_axpyn_dense<false>, dim3(gr), dim3(BLK), lds, st, grp, n, colr, tm, dst, ovf, cur_lut());
     return;
   }
   hipLaunchKernelGGL(k_axpyn, dim3(fgrid(grp, (int64_t)grp.T * dst.C)), dim3(BLK), lds, st, grp, n, colr, L, tm, dst,
