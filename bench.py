@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl1m", help="cl1m (the benchmark), er1000, uneven, serve")
     ap.add_argument("--uneven-n", type=int, default=20_000)
@@ -38,8 +38,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
-    ap.add_argument("--batch-trials", type=int, default=12,
-                    help="colourings solved in one batched call (0: skip the batched measurement)")
+    ap.add_argument("--batch-trials", type=int, default=8,
+                    help="colourings solved plain and in one batched call (0: skip this comparison)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run four copies of 1 GiB on the device, so that hardware byte counters "
                          "collected over this run can be scaled against a kernel of known traffic")
@@ -65,7 +65,7 @@ def query_of(name):
 
 
 KERNEL_OF = {  # profiled op name -> the HIP kernel that runs it
-    "edgejoin": "k_ej", "nodejoin": "k_nj", "axpy": "k_axpy", "merge_root": "k_mroot", "init": "k_init",
+    "edgejoin": "k_ejv", "nodejoin": "k_nj", "axpy": "k_axpyn", "merge_root": "k_mroot", "init": "k_init",
     "merge_u": "k_munary", "merge_v": "k_munary", "merge_edge": "k_medge", "merge_edge_t": "k_medge_t",
     "level_build_sparse": "level build", "light": "k_light", "light_large": "k_light", "leaf": "k_leaf",
     "root_single": "k_root_single",
@@ -91,18 +91,31 @@ def traffic_record(kernel, launches):
     return rec["hbm_bytes_per_launch"]
 
 
-def roofline(stats):
+def roofline(tstats, cstats):
     """The dominant kernel (largest summed time over the timed steps, timed
-    with HIP events on the library's stream) against the HBM peak, from the
-    algorithmic bytes its launches counted."""
+    with HIP events on the library's stream) against the HBM peak.
+
+    tstats: the timed steps (event timing only); cstats: one untimed solve of
+    the first step's colouring with the kernels' algorithmic-byte counters on.
+    Bytes per launch of each operation come from cstats, launch durations from
+    tstats."""
     per_kernel = {}
-    for op, (launches, secs, byts, _work) in stats.items():
+    kern = {}
+    for op, (launches, secs, _b, _w) in tstats.items():
+        cl, _cs, cb, cw = cstats.get(op, (0, 0.0, 0.0, (0, 0, 0)))
+        bpl = cb / cl if cl else 0.0
         kn = kernel_of(op)
         a = per_kernel.setdefault(kn, [0, 0.0, 0.0, []])
         a[0] += launches
         a[1] += secs
-        a[2] += byts
+        a[2] += bpl * launches
         a[3].append(op)
+        kern[op] = {"kernel": kn, "launches": launches, "ms": 1000.0 * secs, "alg_GB_per_launch": bpl / 1e9,
+                    "alg_GBps": bpl * launches / secs / 1e9 if secs > 0 and bpl > 0 else None}
+        if op.startswith("edgejoin") and cl:
+            kern[op]["per_launch_triples_scanned"] = cw[0] / cl
+            kern[op]["per_launch_rows_relaxed"] = cw[1] / cl
+            kern[op]["per_launch_rows_written"] = cw[2] / cl
     name = max(per_kernel, key=lambda x: per_kernel[x][1])
     launches, secs, byts, ops = per_kernel[name]
     ach = byts / secs / 1e9 if secs > 0 else 0.0
@@ -110,10 +123,12 @@ def roofline(stats):
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic, "kernel": name, "ops": sorted(ops), "launches": launches,
             "avg_launch_ms": 1000.0 * secs / max(1, launches), "alg_bytes_per_launch": byts / max(1, launches)}
-    kern = {k: {"launches": v[0], "ms": 1000.0 * v[1], "alg_GB": v[2] / 1e9} for k, v in stats.items()}
-    for k, v in stats.items():
-        if any(v[3]):
-            kern[k]["pairs_scanned"], kern[k]["rows_read"], kern[k]["rows_written"] = v[3]
+    tot_s = sum(v[1] for v in per_kernel.values())
+    tot_b = sum(v[2] for v in per_kernel.values())
+    uncounted = sorted(k for k, v in per_kernel.items() if v[2] == 0)
+    roof["all_kernels"] = {"kernel_s": tot_s, "alg_GB": tot_b / 1e9, "alg_GBps": tot_b / tot_s / 1e9 if tot_s else 0,
+                           "frac": tot_b / tot_s / 1e9 / HBM_PEAK_GBS if tot_s else 0,
+                           "kernels_without_byte_count": uncounted}
     return roof, kern
 
 
@@ -144,6 +159,7 @@ def cpu_baseline(g, k, E, seed, budget_s):
     cpu_total, spent, used, ran, skipped = 0.0, 0.0, [], 0, 0
     last_rate = None
     cores = O.threads()
+    checked = {}  # oracle per-source counts of the sampled sources
     for s_id in np.unique(strata):
         members = cand[strata == s_id]
         members = members[np.argsort(W[members])]
@@ -151,8 +167,9 @@ def cpu_baseline(g, k, E, seed, budget_s):
         sample = members[step // 2::step][:64]
         if spent < budget_s:
             c0, t0 = time.process_time(), time.perf_counter()
-            O.db(g, k, E, chi, reverse_ties=False, sources=sample)
+            _tot, vals = O.db(g, k, E, chi, reverse_ties=False, sources=sample)
             cpu = time.process_time() - c0
+            checked.update({int(s): int(v) for s, v in zip(sample, vals)})
             spent += time.perf_counter() - t0
             last_rate = cpu / W[sample].sum()
             cpu_total += cpu * W[members].sum() / W[sample].sum()
@@ -162,11 +179,38 @@ def cpu_baseline(g, k, E, seed, budget_s):
             cpu_total += last_rate * W[members].sum()
             skipped += len(members)
     wall = cpu_total / cores
-    return dict(value=g.m / wall, unit="colourings*edges/s", cores=cores, kind="oracle",
+    return checked, dict(value=g.m / wall, unit="colourings*edges/s", cores=cores, kind="oracle",
+                cpu_model=cpu_model(), c1_one_thread_s=c1_one_thread_seconds(),
                 sample=(f"DB oracle on {ran} root sources stratified by lower-neighbour degree sum "
                         f"(strata sampled/size: {' '.join(used)}); {skipped} sources in heavier strata priced "
                         f"at the heaviest sampled stratum's CPU s per unit; {spent:.1f} s measured; "
                         f"estimated {cpu_total:.0f} CPU s for the whole solve, / {cores} cores"))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def c1_one_thread_seconds():
+    """The oracle's DB count of the tiny configuration (G(1000, 10/999),
+    5-cycle, k = 5, colouring seed 101) on one thread, in a child process."""
+    import subprocess
+    code = ("import time,sys; sys.path.insert(0, %r)\n"
+            "from cc_inputs import graphs, queries as Q\nfrom oracle import oracle as O\n"
+            "g = graphs.workload_graph('er1000'); k, E = Q.cycle(5); chi = O.colours(g.n, k, 101, 0)\n"
+            "O.db(g, k, E, chi)\nt = time.perf_counter(); O.db(g, k, E, chi); print(time.perf_counter() - t)" % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    try:
+        return float(r.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return None
 
 
 def run_uneven(a):
@@ -286,9 +330,9 @@ def main():
         cc.count(dg, q, seed0 + 1000 + i, trials)
     times, results = [], []
     prof = not a.no_profile
-    if prof:
-        cc.profile_take()
-        cc.profile_enable(True)
+    # timed steps: per-launch HIP events on the library's stream (no counters)
+    cc.profile_take()
+    cc.profile_enable(1 if prof else 0)
     t_all = time.perf_counter()
     for i in range(a.steps):
         t1 = time.perf_counter()
@@ -297,9 +341,8 @@ def main():
         results.append((int(counts[0]), int(ovf[0])))
         print(f"[bench] step {i}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
     total = time.perf_counter() - t_all
-    if prof:
-        cc.profile_enable(False)
-        stats = cc.profile_take()
+    cc.profile_enable(0)
+    tstats = cc.profile_take()
     ms = 1000.0 * total / a.steps
     value = trials * g.m / (total / a.steps)
     out = {
@@ -321,26 +364,46 @@ def main():
         "counts": results,
     }
     if prof:
-        out["roofline"], out["kernels"] = roofline(stats)
+        # untimed: the first step's colouring again, with the kernels' byte counters
+        cc.profile_enable(2)
+        c2 = cc.count(dg, q, seed0, trials)
+        cc.profile_enable(0)
+        cstats = cc.profile_take()
+        assert (int(c2[0][0]), int(c2[1][0])) == results[0], "counting pass disagrees with the timed step"
+        out["roofline"], out["kernels"] = roofline(tstats, cstats)
         # the rate of a plain streaming copy on this device: what an HBM-bound kernel can reach
         out["roofline"]["copy_probe_GBps"] = cc.probe_copy(1 << 30, 10)
     if a.batch_trials > 0:
-        # batched form: one call, trial groups replaying a captured hipGraph,
-        # the trial-group size tuned online on the call's first colourings
-        print(f"[bench] batched: {a.batch_trials} colourings in one call", file=sys.stderr, flush=True)
+        # plain vs batched on the same colourings, neither with profiling:
+        # plain = one cc_count call per colouring; batched = one call of all,
+        # trial groups replaying a captured hipGraph (group size tuned online)
+        B = a.batch_trials
+        print(f"[bench] plain vs batched: {B} colourings each", file=sys.stderr, flush=True)
         t1 = time.perf_counter()
-        bc, bo, be = cc.count_batch(dg, [q], [seed0], [a.batch_trials])
+        pl = [cc.count(dg, q, seed0 + 500 + t, 1) for t in range(B)]
+        dt_plain = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        bc, bo, be = cc.count_batch(dg, [q], [seed0 + 500], [B])
         dt = time.perf_counter() - t1
         rep = cc.last_tune_report()
-        out["batched"] = {"value": a.batch_trials * g.m / dt, "unit": "colourings*edges/s",
-                          "colourings": a.batch_trials, "seconds": dt, "trial_group": rep["trial_group"],
-                          "graph_replays": rep["graph_replays"], "tuning": rep["tried"],
-                          "plain_value": value, "speedup_vs_plain": (a.batch_trials * g.m / dt) / value,
-                          # trial t of seed s is the colouring of seed s + t: the overlap with the plain steps
-                          "counts_match_plain": all(int(bc[i]) == results[i][0] and int(bo[i]) == results[i][1]
-                                                    for i in range(min(a.steps, a.batch_trials)))}
+        out["batched"] = {"value": B * g.m / dt, "unit": "colourings*edges/s", "colourings": B, "seconds": dt,
+                          "trial_group": rep["trial_group"], "graph_replays": rep["graph_replays"],
+                          "tuning": rep["tried"], "plain_value": B * g.m / dt_plain, "plain_seconds": dt_plain,
+                          "speedup_vs_plain": dt_plain / dt,
+                          "counts_match_plain": all(int(bc[t]) == int(pl[t][0][0]) and int(bo[t]) == int(pl[t][1][0])
+                                                    for t in range(B))}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, k, E, seed0, a.cpu_sample_seconds)
+        checked, out["cpu_baseline"] = cpu_baseline(g, k, E, seed0, a.cpu_sample_seconds)
+        # the same colouring on the device with per-source shares: the sampled
+        # sources' shares must equal the oracle's, and they sum to the step's count
+        from oracle import oracle as O
+        chi = O.colours(g.n, k, seed0, 0)
+        _c, _o, ex, per = cc.count_colors(dg, q, chi, per_source=True)
+        bad = [s for s, v in checked.items() if int(per[0][s]) != v]
+        out["oracle_check"] = {"colouring": f"seed {seed0}, trial 0 (step 0)", "sources_checked": len(checked),
+                               "sources_with_matches": sum(1 for v in checked.values() if v),
+                               "mismatches": len(bad), "device_total_equals_step0": int(ex[0]) == results[0][0],
+                               "shares_sum_to_total": sum(int(x) for x in per[0]) == int(ex[0])}
     out["graph_gen_s"] = t_gen
     print(json.dumps(out))
 

@@ -232,23 +232,34 @@ cc_status cc_server_destroy(cc_server s);
 /* ------------------------------------------------------------------ profiling */
 
 /*
- * Per-kernel timing, for measurement only.  While enabled, every kernel launch
- * of cc_count* is bracketed by HIP events on the call's stream; elapsed times
- * are summed per kernel name, together with the algorithmic bytes of the
- * EdgeJoin kernels (counted on the device: 4 bytes per neighbour id scanned,
- * 1 byte per activity check, 8 bytes per slot of every gathered input vector
- * and of every written output vector).  Enabling it slows the calls down.
+ * Per-kernel timing, for measurement only.  Level 1: every kernel launch of
+ * cc_count* (eager runs; graph replays are not split) is bracketed by HIP
+ * events on the call's stream and the elapsed times are summed per operation.
+ * Level 2: in addition the kernels count the algorithmic bytes they move
+ * (Section 5 procedures, the bytes the method itself must read and write):
+ *   EdgeJoin  4 B per (key, trial, lower neighbour) triple scanned -- a key
+ *             being an input row of a source at a neighbour below that source
+ *             -- plus 8 B per slot of every input row relaxed (and of the
+ *             annotating edge's row) plus 8 B per slot of every output row
+ *             actually written (live rows only);
+ *   NodeJoin, AXPY chains, path init, root merge, level builds: the bytes of
+ *             the rows they read and write (8 B per slot, 8-16 B per vertex
+ *             word), counted by the kernels themselves;
+ *   leaf join: computed on the host from the CSR and the table sizes.
+ * The one-workgroup-per-source tier and the merges into non-root tables
+ * report no bytes.  The counters slow the kernels down: time with level 1.
+ * Level 0 turns both off.
  */
 typedef struct {
   char name[32];
   uint64_t launches;
   double seconds;  /* summed event-measured duration */
-  double bytes;    /* algorithmic bytes (EdgeJoin only; 0 elsewhere) */
-  uint64_t work[3]; /* EdgeJoin: (entry, trial, lower neighbour) pairs scanned, input rows read,
-                       output rows written; 0 elsewhere */
+  double bytes;    /* algorithmic bytes (level 2; see above) */
+  uint64_t work[3]; /* EdgeJoin: (key, trial, lower neighbour) triples scanned, input rows relaxed,
+                       output rows written; other kernels: bytes read, bytes written, 0 */
 } cc_kernel_stat;
 
-cc_status cc_profile_enable(int32_t on);
+cc_status cc_profile_enable(int32_t level);
 
 /*
  * A plain streaming copy between two device buffers of `bytes` (a multiple

@@ -310,8 +310,10 @@ def probe_copy(nbytes: int, reps: int = 10) -> float:
     return r.value
 
 
-def profile_enable(on: bool = True):
-    _check(lib().cc_profile_enable(1 if on else 0))
+def profile_enable(level: int = 1):
+    """0: off; 1: per-launch HIP-event timing; 2: timing and the kernels'
+    algorithmic-byte counters."""
+    _check(lib().cc_profile_enable(int(level)))
 
 
 def profile_take():

@@ -252,7 +252,7 @@ cc_status cc_probe_copy(uint64_t bytes, int32_t reps, double *gbps) {
 }
 
 cc_status cc_profile_enable(int32_t on) {
-  return guard([&] { cc::profile_enable(on != 0); });
+  return guard([&] { cc::profile_enable(on); });
 }
 
 cc_status cc_profile_read(cc_kernel_stat *out, int32_t cap, int32_t *len) {

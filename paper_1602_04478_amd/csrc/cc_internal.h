@@ -108,6 +108,12 @@ struct DevGraph {
   std::vector<int32_t> h_rank;      // original id -> rank
   std::vector<int32_t> h_lowcnt;    // number of lower neighbours
   std::vector<int64_t> h_r2;        // two-step high-start reach estimate per source
+  // hub schedule of the dense EdgeJoin: the vertices of degree > 2 * split_chunk
+  // (ranks >= split_lo) as (vertex, neighbour offset) chunks, vertex descending
+  int split_chunk = 0;
+  int64_t split_lo = 0;
+  std::vector<int32_t> h_split_w;   // vertex of each chunk item
+  int32_t *split_items = nullptr;   // device: (vertex, offset) per item
   // device copies
   int64_t *rp = nullptr;
   int32_t *col = nullptr;
@@ -115,6 +121,8 @@ struct DevGraph {
   int32_t *orig = nullptr;
   int32_t *lowcnt = nullptr;
   int device = 0;
+  // items of the hub schedule usable below n_lim: a suffix of the list
+  void split_range(int64_t n_lim, const int32_t **items, int *count) const;
   ~DevGraph();
 };
 
@@ -167,7 +175,7 @@ TuneReport last_tune();  // of the calling thread's last run_batched
 // Device colouring (rank order) for one trial, copied to host by original id.
 void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t stream);
 
-void profile_enable(bool on);
+void profile_enable(int level);  // 0 off, 1 event timing, 2 timing and work counters
 struct KernelProfile {
   std::string name;
   uint64_t launches;

@@ -262,7 +262,7 @@ struct ProfStat {
   uint64_t work[3] = {0, 0, 0};
 };
 std::mutex g_prof_mu;
-bool g_prof_on = false;
+int g_prof_on = 0;  // 1: per-launch event timing; 2: also the kernels' work counters
 std::map<std::string, ProfStat> g_prof;
 
 // Records of the launches of one call (events are resolved at its end).
@@ -288,13 +288,14 @@ void give_event(hipEvent_t e) {
 }
 
 struct Profiler {
-  bool on = false;
+  bool on = false, counting = false;
   hipStream_t st;
   struct Rec {
     std::string name;
     hipEvent_t a, b;
     int ctr;            // counter triple index, or -1
-    double per_scan, per_active, per_entry;
+    double per_scan, per_active, per_entry;  // bytes per unit of each counter
+    double fixed;       // algorithmic bytes known on the host (no counters)
   };
   std::vector<Rec> recs;
   std::vector<uint64_t *> ctrs;
@@ -303,8 +304,9 @@ struct Profiler {
   DevMem ctrmem;
   explicit Profiler(hipStream_t s) : st(s) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    on = g_prof_on;
-    if (on) ctrmem.alloc(sizeof(uint64_t) * 3 * PROF_LANES * kMaxCtr);
+    on = g_prof_on >= 1;
+    counting = g_prof_on >= 2;
+    if (counting) ctrmem.alloc(sizeof(uint64_t) * 3 * PROF_LANES * kMaxCtr);
   }
   // returns a zeroed counter triple for an EdgeJoin launch (or null)
   uint64_t *begin(const char *name, bool counters, double per_scan, double per_active, double per_entry) {
@@ -313,7 +315,7 @@ struct Profiler {
     r.name = name;
     r.ctr = -1;
     uint64_t *c = nullptr;
-    if (counters && nctr < kMaxCtr) {
+    if (counters && counting && nctr < kMaxCtr) {
       r.ctr = nctr++;
       c = ctrmem.as<uint64_t>() + (size_t)3 * PROF_LANES * r.ctr;
       launch_fill_u64(c, 3 * PROF_LANES, st);
@@ -324,8 +326,13 @@ struct Profiler {
     r.per_scan = per_scan;
     r.per_active = per_active;
     r.per_entry = per_entry;
+    r.fixed = 0;
     recs.push_back(r);
     return c;
+  }
+  // algorithmic bytes of the current record computed on the host
+  void add_fixed(double bytes) {
+    if (on && !recs.empty()) recs.back().fixed += bytes;
   }
   void end() {
     if (!on) return;
@@ -347,6 +354,7 @@ struct Profiler {
       ProfStat &p = g_prof[r.name];
       p.launches++;
       p.seconds += ms * 1e-3;
+      p.bytes += r.fixed;
       if (r.ctr >= 0) {
         p.bytes += h[3 * r.ctr] * r.per_scan + h[3 * r.ctr + 1] * r.per_active + h[3 * r.ctr + 2] * r.per_entry;
         for (int i = 0; i < 3; i++) p.work[i] += h[3 * r.ctr + i];
@@ -360,9 +368,9 @@ struct Profiler {
 
 }  // namespace
 
-void profile_enable(bool on) {
+void profile_enable(int level) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_on = on;
+  g_prof_on = level < 0 ? 0 : level > 2 ? 2 : level;
 }
 
 std::vector<KernelProfile> profile_read() {
@@ -966,13 +974,20 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
   for (int64_t i = 1; i < G.B; i++) grp.n_lim = std::max<int64_t>(grp.n_lim, G.hsrc[i]);
   grp.dense = G.dense ? 1 : 0;
   grp.prof = nullptr;
+  grp.hitems = nullptr;
+  grp.nh = 0;
+  grp.split_chunk = g_.split_chunk;
+  grp.split_lo = g_.split_lo;
+  if (G.dense) g_.split_range(grp.n_lim, &grp.hitems, &grp.nh);
+  if (!grp.hitems) grp.nh = 0;
   int max_low = 0;
   for (int64_t i = 0; i < G.B; i++) max_low = std::max(max_low, g_.h_lowcnt[G.hsrc[i]]);
   const int32_t *lowcnt_d = g_.lowcnt;
   std::vector<char> built(P.max_depth + 2, 0);
   std::function<void(int)> build = [&](int d) {  // sparse groups: entries of depth d
     if (G.dense || built[d]) return;
-    if (prof) prof->begin("level_build_sparse", false, 0, 0, 0);
+    // the level kernels count bytes read and written
+    if (prof) grp.prof = prof->begin("level_build_sparse", true, 1.0, 1.0, 0.0);
     if (d == 1) {
       launch_level_init(gd_, grp, lowcnt_d, max_low, leveldev(1), st);
       launch_level_compact(grp, leveldev(1), st);
@@ -982,6 +997,7 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
     }
     HIP_CHECK(hipGetLastError());
     if (prof) prof->end();
+    grp.prof = nullptr;
     built[d] = 1;
   };
   size_t skip_until = 0;  // steps folded into an earlier launch
@@ -1073,7 +1089,8 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
         const double Ce = op.tab >= 0 ? (double)table_C(p_, op.tab) : 0.0;
         grp.prof = prof->begin(nm.c_str(), true, 4.0, 8.0 * (Cin + Ce), 8.0 * Tg * Cout);
       } else {
-        prof->begin(nm.c_str(), false, 0, 0, 0);
+        // the other kernels count their bytes read and written themselves
+        grp.prof = prof->begin(nm.c_str(), true, 1.0, 1.0, 0.0);
       }
     }
     switch (op.kind) {
@@ -1164,7 +1181,17 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
   uint32_t *ovf = d_ovf_.as<uint32_t>();
   if (B.kind == BK_LEAF) {
     int ec = B.edge_child[0];
-    if (prof) prof->begin("leaf", false, 0, 0, 0);
+    if (prof) {
+      // algorithmic bytes of the leaf join: the CSR and colours, per (x, y)
+      // the annotation rows of the edge and of y, per x its own annotation
+      // row and its output row
+      prof->begin("leaf", false, 0, 0, 0);
+      const double n = (double)g_.n, M = (double)g_.m2;
+      auto tc = [&](int blk) { return blk >= 0 ? (double)table_C(p_, blk) : 0.0; };
+      prof->add_fixed(8.0 * (n + 1) + 4.0 * M + (double)Tg * n +
+                      8.0 * Tg * (n * tc(B.node_child[0]) + M * (tc(ec) + tc(B.node_child[1])) +
+                                  n * table_C(p_, (int)bi)));
+    }
     launch_leaf(gd_, Tg, k, colr, tabdev(B.node_child[0]), tabdev(ec), ec >= 0 ? B.edge_first_lo[0] : 0,
                 tabdev(B.node_child[1]), tabs_[bi].as<uint64_t>(), B.size, table_C(p_, (int)bi), ovf, st);
     HIP_CHECK(hipGetLastError());

@@ -5,6 +5,9 @@
 // index (slot of (v,u) for the slot of (u,v)), the lower-neighbour counts and
 // a two-step reach estimate used to schedule sources.
 #include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -18,6 +21,17 @@ DevGraph::~DevGraph() {
   if (rev) (void)hipFree(rev);
   if (orig) (void)hipFree(orig);
   if (lowcnt) (void)hipFree(lowcnt);
+  if (split_items) (void)hipFree(split_items);
+}
+
+void DevGraph::split_range(int64_t n_lim, const int32_t **items, int *count) const {
+  // h_split_w is descending: the items of vertices below n_lim are a suffix
+  // (with greater<>, upper_bound finds the first item whose vertex is < n_lim)
+  auto it = std::upper_bound(h_split_w.begin(), h_split_w.end(), (int32_t)std::min<int64_t>(n_lim, INT32_MAX),
+                             std::greater<int32_t>());
+  const int64_t first = it - h_split_w.begin();
+  *count = (int)((int64_t)h_split_w.size() - first);
+  *items = split_items ? split_items + 2 * first : nullptr;
 }
 
 template <typename F>
@@ -148,7 +162,31 @@ std::unique_ptr<DevGraph> make_graph(int64_t n, const int64_t *row_ptr, const in
     G->h_r2[r] = s;
   });
 
+  // hub schedule of the dense EdgeJoin (a per-degree bucket: vertices of
+  // degree above twice the chunk are cut into chunks of that many neighbours)
+  G->split_chunk = 512;
+  if (const char *ev = getenv("CC_SPLIT_CHUNK")) G->split_chunk = std::max(0, atoi(ev));
+  std::vector<int32_t> items;
+  G->split_lo = n;
+  if (G->split_chunk > 0) {
+    for (int64_t r = n - 1; r >= 0; r--) {
+      const int64_t d = G->h_rp[r + 1] - G->h_rp[r];
+      if (d <= 2 * (int64_t)G->split_chunk) break;  // ranks ascend with degree
+      G->split_lo = r;
+      for (int64_t off = 0; off < d; off += G->split_chunk) {
+        items.push_back((int32_t)r);
+        items.push_back((int32_t)off);
+        G->h_split_w.push_back((int32_t)r);
+      }
+    }
+  }
+
   HIP_CHECK(hipGetDevice(&G->device));
+  if (!items.empty()) {
+    HIP_CHECK(hipMalloc(&G->split_items, sizeof(int32_t) * items.size()));
+    HIP_CHECK(hipMemcpyAsync(G->split_items, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice,
+                             stream));
+  }
   HIP_CHECK(hipMalloc(&G->rp, sizeof(int64_t) * (n + 1)));
   HIP_CHECK(hipMalloc(&G->col, sizeof(int32_t) * std::max<int64_t>(1, G->m2)));
   HIP_CHECK(hipMalloc(&G->rev, sizeof(int64_t) * std::max<int64_t>(1, G->m2)));

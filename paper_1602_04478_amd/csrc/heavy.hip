@@ -79,6 +79,24 @@ __device__ __forceinline__ void mark(uint64_t *m, int64_t v, int b) {
   if (!(m[v] & bit)) atomicOr((unsigned long long *)&m[v], (unsigned long long)bit);
 }
 
+// Work counters of a launch (profiling only; prof null otherwise): each wave
+// adds its three per-thread counts into one of PROF_LANES triples (no hot
+// address).  Every thread of the workgroup calls it.
+__device__ __forceinline__ void prof_flush(uint64_t *prof, uint64_t c0, uint64_t c1, uint64_t c2) {
+  if (!prof) return;
+  for (int o = 32; o > 0; o >>= 1) {
+    c0 += __shfl_xor(c0, o);
+    c1 += __shfl_xor(c1, o);
+    c2 += __shfl_xor(c2, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    uint64_t *pc = prof + 3 * ((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % PROF_LANES);
+    if (c0) atomicAdd((unsigned long long *)&pc[0], (unsigned long long)c0);
+    if (c1) atomicAdd((unsigned long long *)&pc[1], (unsigned long long)c1);
+    if (c2) atomicAdd((unsigned long long *)&pc[2], (unsigned long long)c2);
+  }
+}
+
 // ------------------------------------------------------------------ levels (sparse groups)
 // depth 1: the lower neighbours of each source
 __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_low, LevelDev L) {
@@ -101,9 +119,12 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
   for (int i = threadIdx.x; i < 64; i += BLK) s_u[i] = i < grp.B ? grp.src[i] : 0;
   __syncthreads();
   const int teams = BLK / TEAM, team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  uint64_t prd = 0, pwr = 0;  // profiling: bytes read, written
   for (int64_t v = (int64_t)blockIdx.x * teams + team; v < grp.n_lim; v += (int64_t)gridDim.x * teams) {
     const uint64_t m = Lin.mb[2 * v];
+    prd += lane == 0 ? 8 : 0;
     if (!m) continue;
+    prd += lane == 0 ? 16 : 0;
     int umin = 0x7fffffff, umax = 0;
     for (uint64_t r = m; r; r &= r - 1) {
       const int u = s_u[__builtin_ctzll(r)];
@@ -121,9 +142,14 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
           if (w < s_u[b]) mask |= 1ull << b;
         }
       }
-      if ((Lout.mb[2 * w] & mask) != mask) atomicOr((unsigned long long *)&Lout.mb[2 * w], (unsigned long long)mask);
+      prd += 12;
+      if ((Lout.mb[2 * w] & mask) != mask) {
+        atomicOr((unsigned long long *)&Lout.mb[2 * w], (unsigned long long)mask);
+        pwr += 8;
+      }
     }
   }
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // exclusive prefix sum over the workgroup (BLK threads, all calling); the
@@ -150,7 +176,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t *s, uint32_t
 }
 
 // marks per chunk (thread t reads vertices lo + i * BLK + t: coalesced)
-__global__ void k_cmp_count(const uint64_t *mb, int64_t nv, uint32_t *bcnt) {
+__global__ void k_cmp_count(const uint64_t *mb, int64_t nv, uint32_t *bcnt, uint64_t *prof) {
   __shared__ uint32_t s[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH;
   uint32_t c = 0;
@@ -165,6 +191,7 @@ __global__ void k_cmp_count(const uint64_t *mb, int64_t nv, uint32_t *bcnt) {
     __syncthreads();
   }
   if (threadIdx.x == 0) bcnt[blockIdx.x] = s[0];
+  prof_flush(prof, threadIdx.x == 0 ? 8 * (uint64_t)max((int64_t)0, min((int64_t)CH, nv - lo)) : 0, 0, 0);
 }
 
 // exclusive scan of the chunk counts (one workgroup); total into *cnt
@@ -185,10 +212,11 @@ __global__ void k_cmp_scan(uint32_t *bcnt, int nb, uint32_t *cnt) {
 }
 
 // number the marks: base[v] and the entry list, in (v, b) order
-__global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64_t *list) {
+__global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64_t *list, uint64_t *prof) {
   __shared__ uint32_t s[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH;
   uint32_t run = boff[blockIdx.x];
+  uint64_t prd = 0, pwr = 0;
   for (int i = 0; i < CPER; i++) {
     const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
     const uint64_t mm = v < nv ? mb[2 * v] : 0;
@@ -198,9 +226,12 @@ __global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64
       mb[2 * v + 1] = id0;
       uint32_t id = id0;
       for (uint64_t r = mm; r; r &= r - 1) list[id++] = v * 64 + __builtin_ctzll(r);
+      prd += 8;
+      pwr += 8 + 8 * (uint64_t)__popcll(mm);
     }
     run += tot;
   }
+  prof_flush(prof, prd, pwr, 0);
 }
 
 // ------------------------------------------------------------------ INIT
@@ -216,7 +247,7 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
   const int64_t per = (int64_t)T * C;
   const int64_t N = (int64_t)grp.B * max_low * per;
   const int sa = nt.val ? nt.s : 1;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     const int64_t en = i / per;
     const int r = (int)(i - en * per), t = r / C, c = r - t * C;
@@ -247,8 +278,11 @@ __global__ void k_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_
     dst.val[e * per + r] = acc;
     if (grp.dense && r == 0) atomicOr((unsigned long long *)&dst.mask[x], 1ull << b);
     if (of) ofm |= 1ull << t;
+    pwr += 8;
+    if (c == 0) prd += 4 + 2 + 8 * ((nt.val ? nt.C : 0) + (et.val ? et.C : 0));
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // ------------------------------------------------------------------ EdgeJoin
@@ -351,7 +385,7 @@ __global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uin
               ok = cv != cu && cv != cw;
             }
           }
-          n_scan += in;
+          n_scan += id >= 0;  // a key of source b at v below u_b
           n_rows += ok;
           const uint64_t okm = __ballot(ok);
           const bool stop = __ballot(!in) != 0;
@@ -560,22 +594,43 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
   uint32_t n_scan = 0, n_rows = 0, n_ent = 0;  // profile counts of this lane (each below 2^32 per launch)
   uint64_t mlo = 0, mhi = 0;  // this lane's root-merge sum (its trial)
   constexpr int WPB = NB / WAVE;  // wavefronts per workgroup
-  // vertex ids fit 31 bits (the graph's limit), so they travel as int
-  const uint32_t nlim = (uint32_t)grp.n_lim, wstride = gridDim.x * WPB * NG;
-  for (uint32_t wl = (blockIdx.x * WPB + tid / WAVE) * NG + lane / SW; wl < nlim; wl += wstride) {
-    const int w = (int)wl;
+  // Work items.  Dense groups with a hub schedule: first the chunks of the
+  // hubs' neighbour lists (a wavefront each, partial rows added atomically
+  // into rows cleared before the launch), then the other vertices from the
+  // highest down.  Otherwise one item per output vertex, ascending.
+  // Vertex ids fit 31 bits (the graph's limit), so they travel as int.
+  const bool hsplit = !EPI && grp.dense && grp.nh > 0;
+  const uint32_t nh = hsplit ? (uint32_t)grp.nh : 0u;
+  const uint32_t nlight = (uint32_t)(hsplit ? min(grp.n_lim, grp.split_lo) : grp.n_lim);
+  const uint32_t nitems = nh + nlight, wstride = gridDim.x * WPB * NG;
+  for (uint32_t wl = (blockIdx.x * WPB + tid / WAVE) * NG + lane / SW; wl < nitems; wl += wstride) {
+    int w;
+    int64_t r0, r1;  // the item's neighbour range
+    bool split = false, first_chunk = true;
+    if (wl < nh) {
+      w = grp.hitems[2 * wl];
+      const int off = grp.hitems[2 * wl + 1];
+      const int64_t a1 = g.rp[w + 1];
+      r0 = g.rp[w] + off;
+      r1 = min(a1, r0 + (int64_t)grp.split_chunk);
+      split = true;
+      first_chunk = off == 0;
+    } else {
+      w = hsplit ? (int)(nlight - 1u - (wl - nh)) : (int)wl;
+      // w's edge range is loaded with its marks, not after them (one step
+      // less on the chain of dependent loads)
+      r0 = g.rp[w];
+      r1 = g.rp[w + 1];
+    }
     // output rows at w: dense -- every source above w; sparse -- the marks
     uint64_t ob = 0;
-    // w's edge range is loaded with its marks, not after them (one step less
-    // on the chain of dependent loads)
-    const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
     if (grp.dense) {
       for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_src[i + gl] > w) << i;
     } else {
       ob = Lout.mb[2 * (int64_t)w];
     }
     if (!ob) {
-      if (grp.dense && gl == 0)
+      if (grp.dense && gl == 0 && !split)
         for (int j = 0; j < epi.nregs; j++)
           if (epi.regs[j].write) epi.regs[j].r.mask[w] = 0;
       continue;
@@ -620,8 +675,16 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
           }
           inb &= pass;
         }
-        const uint64_t below = gballot(vj != VNONE);
-        n_scan += act ? (uint32_t)__popcll(below) : 0u;
+        if (grp.prof) {
+          // (key, trial, lower neighbour) triples: the pass's sources b with an
+          // input row at v = vj (bit set in inb), v below u_b, and a trial in
+          // which b is not idle at w (its colour differs from w's)
+          for (uint64_t r = inb; r; r &= r - 1) {
+            const int uq = s_src[__builtin_ctzll(r)];
+            if (vj < uq)
+              for (int t = 0; t < T; t++) n_scan += colr[(int64_t)t * n + uq] != colr[(int64_t)t * n + w] ? 1u : 0u;
+          }
+        }
         uint64_t todo = gballot(inb != 0);
         const bool stop = gballot(vj == VNONE) != 0;
         // one trial: the neighbour's colour travels with it (loaded by its own lane)
@@ -903,19 +966,32 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
         if (grp.dense)
           for (int o = SW / 2; o > 0; o >>= 1) mine |= (uint64_t)__shfl_xor(mine, o, SW);
         if (grp.dense && gl == 0) s_live[j * (NB / SW) + tid / SW] |= mine;
-        if (b >= 0 && (!grp.dense || ((mine >> b) & 1ull))) {
+        const bool wr = b >= 0 && (!grp.dense || ((mine >> b) & 1ull));
+        if (wr) {
           const int64_t id = grp.dense ? (int64_t)w * B + b : sparse_entry(R.L, w, b);
           uint64_t *drow = R.r.val + (id * T + lt) * Cj;
-          for (int o = 0; o < Cj; o++) drow[o] = accs[(R.col + o) * NB + tid];
+          if (split) {  // a chunk of a hub: add the partial row (checked through the old value)
+            for (int o = 0; o < Cj; o++) {
+              const uint64_t x = accs[(R.col + o) * NB + tid];
+              if (!x) continue;
+              const uint64_t old = atomicAdd((unsigned long long *)&drow[o], (unsigned long long)x);
+              if (old + x < old) ofm |= 1ull << lt;
+            }
+          } else {
+            for (int o = 0; o < Cj; o++) drow[o] = accs[(R.col + o) * NB + tid];
+          }
         }
+        // rows (w, b) written, all their trials (a hub's rows once, by its first chunk)
+        if (b >= 0 && lt == 0 && (split ? first_chunk : wr)) n_ent++;
       }
     }
-    if (gl == 0) {
-      if (grp.dense)
-        for (int j = 0; j < epi.nregs; j++)
-          if (epi.regs[j].write) epi.regs[j].r.mask[w] = s_live[j * (NB / SW) + tid / SW];
-      n_ent += (uint32_t)__popcll(ob);
-    }
+    if (gl == 0 && grp.dense)
+      for (int j = 0; j < epi.nregs; j++) {
+        if (!epi.regs[j].write) continue;
+        const uint64_t lv = s_live[j * (NB / SW) + tid / SW];
+        if (!split) epi.regs[j].r.mask[w] = lv;
+        else if (lv) atomicOr((unsigned long long *)&epi.regs[j].r.mask[w], (unsigned long long)lv);
+      }
   }
   flag_trials(ovf, ofm);
   if (EPI) {
@@ -961,7 +1037,7 @@ __global__ __launch_bounds__(BLK) void k_nj(GroupDev grp, int64_t n, const uint8
   const int rA = nt.s - 1;
   const int64_t per = (int64_t)T * C;
   const int64_t N = nentries(grp, L) * per;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     const int64_t e = i / per;
     const int r = (int)(i - e * per), t = r / C, c = r - t * C;
@@ -969,12 +1045,14 @@ __global__ __launch_bounds__(BLK) void k_nj(GroupDev grp, int64_t n, const uint8
     int b;
     entry_vb(grp, L, e, v, b);
     if (!live(grp, a, v, b)) continue;
+    pwr += 8;
     const int64_t u = grp.src[b];
     uint64_t acc = 0;
     bool of = false;
     if (v < u) {
       const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
       if (cu != cv) {
+        if (c == 0) prd += 8 * (uint64_t)(Ca + nt.C);
         const uint32_t Rp = spread2(unrank(lut, dst.s - 2, c), cu, cv);
         const uint64_t *ar = a.val + (e * T + t) * Ca;
         const uint64_t *nr = nt.val + (v * T + t) * nt.C;
@@ -996,6 +1074,7 @@ __global__ __launch_bounds__(BLK) void k_nj(GroupDev grp, int64_t n, const uint8
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // ------------------------------------------------------------------ AXPY
@@ -1004,21 +1083,27 @@ __global__ __launch_bounds__(BLK) void k_axpy(GroupDev grp, LevelDev L, RegDev a
                                               uint32_t *ovf) {
   const int T = grp.T, C = dst.C;
   const int64_t N = nentries(grp, L) * T * C;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     bool of = false;
-    bool on = true;
+    bool on = true, dlive = true;
     if (grp.dense) {
+      // dense registers are pooled: a row whose activity bit is clear holds
+      // whatever an earlier group left there and counts as zero
       const int64_t row = i / ((int64_t)T * C);
       on = (a.mask[row / grp.B] >> (row % grp.B)) & 1ull;
+      dlive = !first && ((dst.mask[row / grp.B] >> (row % grp.B)) & 1ull);
       if (!on && !first) continue;
     }
-    uint64_t y = first ? 0 : dst.val[i];
+    uint64_t y = (first || !dlive) ? 0 : dst.val[i];
     if (on) add_ck(y, mul_ck(w, a.val[i], of), of);
     dst.val[i] = y;
     if (of) ofm |= 1ull << ((i / C) % T);
+    prd += 8 * ((on ? 1 : 0) + (!first && dlive ? 1 : 0));
+    pwr += 8;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // dst = sum of w_i * a_i over up to four terms (an AXPY chain in one pass)
@@ -1101,12 +1186,13 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
   __syncthreads();
   const int64_t per = (int64_t)T * C;
   const int64_t N = nentries(grp, L) * per;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     bool of = false;
     uint64_t y = 0;
     const int64_t row = i / per;
     const int r = (int)(i - row * per), t = r / C, c = r - t * C;
+    pwr += 8;
     for (int q = 0; q < tm.n; q++) {
       if (grp.dense && !((tm.a[q].mask[row / grp.B] >> (row % grp.B)) & 1ull)) continue;
       uint64_t x;
@@ -1118,6 +1204,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
         const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
         x = 0;
         if (v < u && cu != cv) {
+          if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
           if (tm.jmw[q]) {
             const int ns = tm.jns[q];
             const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
@@ -1130,6 +1217,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
         }
       } else {
         x = tm.a[q].val[i];
+        prd += 8;
       }
       if (x) add_ck(y, mul_ck(tm.w[q], x, of), of);
     }
@@ -1137,6 +1225,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 __global__ void k_mask_orn(AxpyTerms tm, uint64_t *dm, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1187,9 +1276,10 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
   const int per = T * C;
   const int lane = threadIdx.x % 64;
   const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;
   for (int64_t v = wave; v < grp.n_lim; v += nwave) {
     const uint64_t m = a.mask[v];
+    prd += lane == 0 ? 8 : 0;
     if (!m) continue;
     const int items = __popcll(m) * per;
     for (int it = lane; it < items; it += 64) {
@@ -1202,6 +1292,7 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
       if (v < u) {
         const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
         if (cu != cv) {
+          if (c == 0) prd += 8 * (uint64_t)(Ca + nt.C);
           const uint32_t Rp = spread2(s_uo[c], cu, cv);
           const uint64_t *ar = a.val + (e * T + t) * Ca;
           const uint64_t *nr = nt.val + (v * T + t) * nt.C;
@@ -1221,9 +1312,11 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
       }
       dst.val[e * per + r] = acc;
       if (of) ofm |= 1ull << t;
+      pwr += 8;
     }
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // JM: every NodeJoin term has a split map (the subset walk is not compiled in)
@@ -1244,9 +1337,13 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
   const int per = T * C;
   const int lane = threadIdx.x % 64;
   const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;
   for (int64_t v = wave; v < grp.n_lim; v += nwave) {
     uint64_t mt[4] = {0, 0, 0, 0};
+    if (lane == 0) {
+      prd += 8 * (uint64_t)tm.n;
+      pwr += 8;
+    }
     uint64_t m = 0;
 #pragma unroll
     for (int q = 0; q < 4; q++)
@@ -1274,6 +1371,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
           const int cu = s_cu[t * WAVE + b], cv = T == 1 ? cv1 : colr[(int64_t)t * n + v];
           x = 0;
           if (v < u && cu != cv) {
+            if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
             if (JM || tm.jmw[q]) {
               const int ns = tm.jns[q];
               const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
@@ -1287,14 +1385,17 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
           }
         } else {
           x = tm.a[q].val[i];
+          prd += 8;
         }
         if (x) add_ck(y, mul_ck(tm.w[q], x, of), of);
       }
       dst.val[i] = y;
       if (of) ofm |= 1ull << (r / C);
+      pwr += 8;
     }
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // ------------------------------------------------------------------ root merge
@@ -1317,7 +1418,7 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
   for (int c = threadIdx.x; c < Ca; c += BLK) s_yi[c] = lut[LUT_RANK + (Kp & ~unrank(lut, a.s - 2, c))];
   __syncthreads();
   const int64_t N = nentries(grp, La);
-  uint64_t tlo = 0, thi = 0;
+  uint64_t tlo = 0, thi = 0, prd = 0;
   for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < N; e += (int64_t)gridDim.x * BLK) {
     int64_t v;
     int b;
@@ -1329,6 +1430,7 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
     for (int t = 0; t < T; t++) {
       const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
       if (cu == cv) continue;
+      prd += 16 * (uint64_t)Ca;
       const uint64_t *ar = a.val + (e * T + t) * Ca;
       const uint64_t *br = bb.val + (eb * T + t) * Cb;
       uint64_t lo = 0, hi = 0;
@@ -1372,6 +1474,7 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
   __syncthreads();
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (s_acc[2 * t] | s_acc[2 * t + 1]) atomic_add128(&acc.sum[2 * t], s_acc[2 * t], s_acc[2 * t + 1]);
+  prof_flush(grp.prof, prd, 0, 0);
 }
 
 // ------------------------------------------------------------------ merges into unary tables
@@ -1577,9 +1680,9 @@ int fgrid(const GroupDev &grp, int64_t per_entry) {
 static void compact(const GroupDev &grp, LevelDev L, hipStream_t st) {
   const int64_t nv = grp.n_lim;
   const int nb = (int)((nv + CH - 1) / CH);
-  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt);
+  hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, grp.prof);
   hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(BLK), 0, st, L.bcnt, nb, L.cnt);
-  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, L.list);
+  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, L.list, grp.prof);
 }
 
 int64_t level_chunks(int64_t n_lim) { return (n_lim + CH - 1) / CH; }
@@ -1773,6 +1876,13 @@ static bool njmap_find(int k, int ro, int rA, int C, int Ca, int Cn, const uint3
 void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                    const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st) {
   const bool ep = epi.nops > 0;
+  if (!ep && grp.dense && grp.nh > 0 && grp.split_lo < grp.n_lim) {
+    // the hubs' rows and activity words start at zero: their chunks add into them
+    const RegDev &d = epi.regs[0].r;
+    const int64_t per = (int64_t)grp.B * grp.T * d.C;
+    launch_fill_u64(d.val + grp.split_lo * per, (grp.n_lim - grp.split_lo) * per, st);
+    launch_fill_u64(d.mask + grp.split_lo, grp.n_lim - grp.split_lo, st);
+  }
   const uint32_t *em = nullptr;
   int emw = 0, emcp = 0;
   const bool mp = !etab.val && !getenv_flag_off("CC_EJMAP") && ejmap_find(grp.k, a.s - 2, a.C, &em, &emw, &emcp);

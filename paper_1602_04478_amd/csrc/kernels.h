@@ -52,7 +52,16 @@ struct GroupDev {
   int k;
   int64_t n_lim;      // every frontier vertex is below this rank
   int dense;          // 1: domain = all (v, b) with v < n_lim; 0: the register's list
-  uint64_t *prof;     // optional counters: [edges scanned, active in-neighbours, entries written]
+  uint64_t *prof;     // optional work counters of the launch (profiling)
+  // Dense EdgeJoin hub schedule: output vertices of rank >= split_lo (below
+  // n_lim) have their neighbour lists cut into chunks of split_chunk
+  // neighbours, one work item each (hitems: (vertex, first neighbour offset)
+  // pairs, nh of them, heaviest first); the others are one item per vertex.
+  // nh = 0: no split.
+  const int32_t *hitems;
+  int nh;
+  int split_chunk;
+  int64_t split_lo;
 };
 
 struct GraphDev {

@@ -46,6 +46,9 @@ PATH_MODES = {
     "fused-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_FUSE": "1"},
     "nomap-dense": {"CC_DENSE": "all", "CC_EJMAP": "0", "CC_NJMAP": "0"},
     "nomap-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJMAP": "0", "CC_NJMAP": "0"},
+    # hub schedule with tiny chunks: every vertex of degree > 4 runs as chunks of 2 neighbours
+    "dense-split": {"CC_DENSE": "all", "CC_SPLIT_CHUNK": "2"},
+    "dense-split3": {"CC_DENSE": "all", "CC_SPLIT_CHUNK": "3"},
 }
 
 
@@ -87,6 +90,8 @@ def test_small_shapes_match_oracle(small_graphs, name, dense_mode):
 
 ONE_TRIAL_MODES = {
     "dense": {"CC_DENSE": "all"},
+    "dense-split": {"CC_DENSE": "all", "CC_SPLIT_CHUNK": "2"},
+    "dense-split-unpacked": {"CC_DENSE": "all", "CC_SPLIT_CHUNK": "3", "CC_EJPACK": "0"},
     "dense-unpacked": {"CC_DENSE": "all", "CC_EJPACK": "0"},
     "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
     "sparse-unpacked": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJPACK": "0"},
