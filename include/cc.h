@@ -166,6 +166,28 @@ cc_status cc_count_colors(cc_graph g, cc_query q, int32_t trials, const uint8_t 
                           void *stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as cc_count, but the call allocates nothing
+ * on the device (no hipMalloc / hipFree, no stream or event creation): every
+ * device buffer of the solve is carved from a static scratch of
+ * CC_STATIC_SCRATCH_BYTES per device, held by the library from its first use
+ * on that device until the process ends.  Solves whose buffers do not fit
+ * fail with CC_E_NOMEM (before any device work).  Calls on one device share
+ * its scratch, so the library runs them one at a time (a call waits for the
+ * previous one on that device); overlapping calls from other threads are
+ * serialised, never interleaved.  Every buffer is cleared or written by the
+ * solve before it is read, so the scratch's earlier contents do not matter.
+ * The sources with small reach run in the grouped path (the one-workgroup
+ * tier's scratch would not fit), and profiling is ignored.  `stream` NULL:
+ * the null stream.  The device tables of the kernels (colex and slot maps)
+ * live in static device memory as well.
+ */
+#define CC_STATIC_SCRATCH_BYTES (256ull << 20)
+cc_status cc_count_static(cc_graph g, cc_query q, uint64_t seed, int32_t trials, uint64_t *counts,
+                          uint8_t *overflow, cc_u128 *exact, double *estimate, void *stream);
+
+/*
  * Batched form: nq queries on one graph, query i with trials[i] colourings
  * from seeds[i] (trial t of query i uses the colouring (seeds[i], t) of the
  * contract, so the counts equal cc_count's).  The colourings of a query are

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcc.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "heavy.hip", "light.hip", "planner.cpp", "graph.cpp", "executor.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "heavy.hip", "light.hip", "planner.cpp", "graph.cpp", "executor.cpp", "api.cpp", "server.cpp", "static_mem.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

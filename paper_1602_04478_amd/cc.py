@@ -19,7 +19,7 @@ STATUS = {0: "CC_OK", 1: "CC_E_ARG", 2: "CC_E_GRAPH", 3: "CC_E_QUERY_TW", 4: "CC
 
 # every entry point declared in include/cc.h
 EXPORTS = ["cc_graph_create", "cc_graph_destroy", "cc_graph_info", "cc_query_create", "cc_query_destroy",
-           "cc_query_info", "cc_query_plan", "cc_footprint", "cc_colors", "cc_count", "cc_count_colors",
+           "cc_query_info", "cc_query_plan", "cc_footprint", "cc_colors", "cc_count", "cc_count_static", "cc_count_colors",
            "cc_count_batch", "cc_server_create", "cc_server_add_graph", "cc_server_submit", "cc_server_poll",
            "cc_server_drain", "cc_server_destroy", "cc_last_tune_report", "cc_profile_enable", "cc_profile_read", "cc_probe_copy",
            "cc_status_str", "cc_last_error"]
@@ -71,6 +71,7 @@ def lib():
         "cc_footprint": [vp, vp, i32, P(u64)],
         "cc_colors": [vp, i32, u64, i32, vp],
         "cc_count": [vp, vp, u64, i32, vp, vp, vp, vp, vp],
+        "cc_count_static": [vp, vp, u64, i32, vp, vp, vp, vp, vp],
         "cc_count_colors": [vp, vp, i32, vp, vp, vp, vp, vp, vp],
         "cc_count_batch": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "cc_server_create": [u64, i32, P(vp)],
@@ -207,6 +208,19 @@ def count(g: Graph, q: Query, seed: int, trials: int = 1, stream=None):
     est = ctypes.c_double()
     _check(lib().cc_count(g.h, q.h, seed & (2**64 - 1), trials, _ptr(counts), _ptr(ovf), ex,
                           ctypes.byref(est), stream))
+    exact = [e.lo | (e.hi << 64) for e in ex]
+    return counts, ovf, exact, est.value
+
+
+def count_static(g: Graph, q: Query, seed: int, trials: int = 1, stream=None):
+    """cc_count_static: as count, with every device buffer carved from the
+    library's static scratch (no device allocation)."""
+    counts = np.zeros(trials, dtype=np.uint64)
+    ovf = np.zeros(trials, dtype=np.uint8)
+    ex = (U128 * trials)()
+    est = ctypes.c_double()
+    _check(lib().cc_count_static(g.h, q.h, seed & (2**64 - 1), trials, _ptr(counts), _ptr(ovf), ex,
+                                 ctypes.byref(est), stream))
     exact = [e.lo | (e.hi << 64) for e in ex]
     return counts, ovf, exact, est.value
 

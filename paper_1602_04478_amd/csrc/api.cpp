@@ -187,6 +187,25 @@ cc_status cc_count(cc_graph g, cc_query q, uint64_t seed, int32_t trials, uint64
   });
 }
 
+cc_status cc_count_static(cc_graph g, cc_query q, uint64_t seed, int32_t trials, uint64_t *counts,
+                          uint8_t *overflow, cc_u128 *exact, double *estimate, void *stream) {
+  return guard([&] {
+    if (!g || !q || !counts || !overflow || trials < 1) cc::fail(CC_E_ARG, "bad argument");
+    const int dev = g->g->device;
+    HIP_CHECK(hipSetDevice(dev));
+    // one solve at a time per device: they share its scratch
+    std::lock_guard<std::mutex> lk(cc::static_scratch_lock(dev));
+    cc::ExecOptions o;
+    o.arena = cc::static_scratch(dev);
+    o.arena_bytes = cc::kStaticScratchBytes;
+    cc::ColourSource cs;
+    cs.from_seed = true;
+    cs.seed = seed;
+    auto r = cc::run_count(*g->g, q->plan, trials, cs, o, (hipStream_t)stream, nullptr);
+    write_results(q->plan, r, trials, counts, overflow, exact, estimate);
+  });
+}
+
 cc_status cc_count_colors(cc_graph g, cc_query q, int32_t trials, const uint8_t *colors, uint64_t *counts,
                           uint8_t *overflow, cc_u128 *exact, cc_u128 *per_source, void *stream) {
   return guard([&] {

@@ -142,6 +142,11 @@ struct ExecOptions {
   int use_graphs = 0;
   int dense_sources = -1;         // sources run as dense groups (-1: the cost model's cut)
   uint64_t mem_budget = 0;        // bytes; 0 = from the device's free memory
+  // Allocation-free solve: every device buffer is carved from [arena,
+  // arena + arena_bytes) (no hipMalloc, no stream or event creation, no
+  // one-workgroup tier, no profiling).  Null: the block cache.
+  uint8_t *arena = nullptr;
+  uint64_t arena_bytes = 0;
 };
 
 // Colours in rank order for `trials` trials: either from (seed) by the
@@ -187,6 +192,15 @@ void dump_programs(const Plan &p);  // the cycle programs, to stderr
 double probe_copy(uint64_t bytes, int reps);  // GB/s of a plain device copy (read + write)
 
 double estimate_from(const Plan &p, const std::vector<u128> &exact, const std::vector<uint8_t> &ovf);
+
+// ------------------------------------------------------------------ static device memory (static_mem.hip)
+// Size of `scratch`, the per-device work memory of cc_count_static.
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+// Device address of this device's scratch (looked up once per device; the
+// device must be current).  Throws CC_E_DEVICE when the lookup fails.
+uint8_t *static_scratch(int dev);
+// Serialises the calls that use one device's scratch.
+std::mutex &static_scratch_lock(int dev);
 
 }  // namespace cc
 

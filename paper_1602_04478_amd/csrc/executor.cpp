@@ -85,15 +85,36 @@ size_t cache_bytes(int dev) {
   return c.cached[dev];
 }
 
+// An allocation-free solve carves its device buffers from a caller-given
+// region instead (see ExecOptions::arena): blocks are never returned to it,
+// the whole region is reused by the next such solve.
+struct Arena {
+  uint8_t *base = nullptr;
+  size_t size = 0, used = 0;
+};
+thread_local Arena *g_arena = nullptr;
+
 struct DevMem {
   void *p = nullptr;
   size_t bytes = 0;
   int dev = 0;
+  bool carved = false;  // from the arena (not the block cache)
   DevMem() = default;
   explicit DevMem(size_t b) { alloc(b); }
   void alloc(size_t b) {
     release();
     if (b == 0) b = 8;
+    if (g_arena) {
+      const size_t a = (b + 255) & ~(size_t)255;
+      if (g_arena->used + a > g_arena->size)
+        fail(CC_E_NOMEM, "the solve needs more than the static scratch of " + std::to_string(g_arena->size) +
+                             " bytes");
+      p = g_arena->base + g_arena->used;
+      g_arena->used += a;
+      bytes = a;
+      carved = true;
+      return;
+    }
     b = round_block(b);
     dev = cur_device();
     size_t got = 0;
@@ -115,16 +136,18 @@ struct DevMem {
     bytes = b;
   }
   void release() {
-    if (p) cache_give(dev, p, bytes);
+    if (p && !carved) cache_give(dev, p, bytes);
     p = nullptr;
     bytes = 0;
+    carved = false;
   }
   ~DevMem() { release(); }
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
-  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) {
+  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev), carved(o.carved) {
     o.p = nullptr;
     o.bytes = 0;
+    o.carved = false;
   }
   DevMem &operator=(DevMem &&o) noexcept {
     if (this != &o) {
@@ -132,8 +155,10 @@ struct DevMem {
       p = o.p;
       bytes = o.bytes;
       dev = o.dev;
+      carved = o.carved;
       o.p = nullptr;
       o.bytes = 0;
+      o.carved = false;
     }
     return *this;
   }
@@ -204,7 +229,7 @@ int light_grid(int device) {
 struct Bytes {
   uint64_t fixed, per_B;
 };
-Bytes solver_bytes(const DevGraph &g, const Plan &p, int T) {
+Bytes solver_bytes(const DevGraph &g, const Plan &p, int T, bool noalloc = false) {
   const uint64_t n = (uint64_t)std::max<int64_t>(1, g.n);
   // registers are pooled by index across the programs: register r holds the
   // widest row any program puts there
@@ -222,8 +247,9 @@ Bytes solver_bytes(const DevGraph &g, const Plan &p, int T) {
   b.fixed = table_bytes(g, p, T) + 2 * n * T                   // tables, colours (+ host-colour staging)
             + nregs * 8 * n                                    // activity masks
             + (uint64_t)dmax * (16 * n + 4 * (n / 4096 + 2))   // level marks and bases
-            + (uint64_t)light_scratch_bytes(g, T) * light_grid(g.device) + (64 << 20)
-            + (large_light_on() ? (uint64_t)(32 << 20) * (light_grid(g.device) / 3) : 0);  // large light stage
+            + (noalloc ? (uint64_t)(1 << 20)  // no one-workgroup tier; alignment of the carved buffers
+                       : (uint64_t)light_scratch_bytes(g, T) * light_grid(g.device) + (64 << 20) +
+                             (large_light_on() ? (uint64_t)(32 << 20) * (light_grid(g.device) / 3) : 0));
   b.per_B = 8 * n * T * slots + (uint64_t)dmax * 8 * n;        // registers, level lists
   return b;
 }
@@ -241,7 +267,7 @@ Sizing choose(const DevGraph &g, const Plan &p, int trials, const ExecOptions &o
   if (cmax > max_row_slots()) fail(CC_E_UNSUPPORTED, "signature tables too wide for one workgroup");
   while ((int64_t)z.T * cmax > max_row_slots()) z.T = std::max(1, z.T / 2);
   for (;;) {
-    Bytes b = solver_bytes(g, p, z.T);
+    Bytes b = solver_bytes(g, p, z.T, opt.arena != nullptr);
     int64_t B = budget > b.fixed && b.per_B ? (int64_t)((budget - b.fixed) / b.per_B) : 0;
     if (B >= 1 || z.T == 1) {
       if (B < 1) fail(CC_E_NOMEM, "plan does not fit the device memory budget");
@@ -302,7 +328,8 @@ struct Profiler {
   static constexpr int kMaxCtr = 16384;
   int nctr = 0;
   DevMem ctrmem;
-  explicit Profiler(hipStream_t s) : st(s) {
+  explicit Profiler(hipStream_t s, bool allowed = true) : st(s) {
+    if (!allowed) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     on = g_prof_on >= 1;
     counting = g_prof_on >= 2;
@@ -707,14 +734,14 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
     : g_(g), p_(p), opt_(opt), st_(st) {
   if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
   HIP_CHECK(hipSetDevice(g.device));
-  if (!st_) {  // the null stream cannot be captured: work on a stream of our own
+  if (!st_ && !opt.arena) {  // the null stream cannot be captured: work on a stream of our own
     HIP_CHECK(hipStreamCreate(&own_st_));
     st_ = own_st_;
     st = st_;
   }
   const int k = p.k;
   if (!ejmaps_prepare(k)) fail(CC_E_DEVICE, "EdgeJoin slot maps: device allocation failed");
-  uint64_t budget = opt.mem_budget ? opt.mem_budget : (uint64_t)(free_bytes() * 0.85);
+  uint64_t budget = opt.arena ? opt.arena_bytes : opt.mem_budget ? opt.mem_budget : (uint64_t)(free_bytes() * 0.85);
   z_ = choose(g, p, trials, opt, budget);
   const int T = z_.T;
   gd_ = GraphDev{g.rp, g.col, g.rev, g.n, g.m2};
@@ -743,6 +770,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   }
   if (const char *ev = getenv("CC_LIGHT"))
     if (!strcmp(ev, "0")) use_light_ = false;
+  if (opt.arena) use_light_ = false;  // its per-workgroup scratch would not fit
   light_scratch_ = light_scratch_bytes(g, T);
   if (const char *ev = getenv("CC_FALLBACK"))
     if (!strcmp(ev, "dense")) fallback_dense_ = true;
@@ -873,7 +901,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   // the large stage (CC_LIGHT_LARGE=1): one workgroup per compute unit.  Off by
   // default: on the 1e6-vertex workload it takes 9.7k of the 23k hand-backs
   // in 0.26 s but saves the grouped path only about as much.
-  use_large_ = large_light_on();
+  use_large_ = large_light_on() && !opt.arena;
   if (const char *ev = getenv("CC_LIGHT_SCRATCH_LARGE")) light_scratch_large_ = std::max<int64_t>(4096, atoll(ev));
   light2_.resize(p.blocks.size());
   if (use_large_) {
@@ -1318,7 +1346,7 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
     HIP_CHECK(hipMemcpyAsync(d_hcol_.p, cs.host + (size_t)t0 * g_.n, (size_t)g_.n * Tg, hipMemcpyHostToDevice, st));
     launch_permute_colours(d_hcol_.as<uint8_t>(), g_.orig, g_.n, Tg, d_col_.as<uint8_t>(), st);
   }
-  Profiler prof(st);
+  Profiler prof(st, !opt_.arena);
   const bool graphs = opt_.use_graphs && probed && cs.from_seed && !per_source && !prof.on;
   if (graphs) {
     if (!exec_ || exec_T_ != Tg) {
@@ -1381,6 +1409,14 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
 CountResult run_count(const DevGraph &g, const Plan &p, int trials, const ColourSource &cs, const ExecOptions &opt,
                       hipStream_t st, std::vector<u128> *per_source) {
   if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
+  // allocation-free: every DevMem of this solve (all made on this thread) is
+  // carved from the given region
+  Arena arena{opt.arena, (size_t)opt.arena_bytes, 0};
+  struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a) : prev(g_arena) { g_arena = a; }
+    ~ArenaScope() { g_arena = prev; }
+  } scope(opt.arena ? &arena : g_arena);
   Solver S(g, p, trials, opt, st);
   CountResult res;
   res.exact.assign(trials, 0);

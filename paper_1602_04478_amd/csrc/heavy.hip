@@ -1724,7 +1724,8 @@ bool epi_fits(int ncols, int T, int etab_C) {
 // to one of colour cw -- the rank of (R + cv) with cu and cw squeezed out,
 // where R is slot c's colour set spread around cu and cv -- or 0xff when cw is
 // in R or the three colours are not distinct.  Rows padded to four slots.
-// Built on the host once per device and k, kept until the process ends.
+// Built on the host once per device and k, kept in the constant-table pool
+// (static device memory) until the process ends.
 constexpr size_t EJMAP_MAX = 16384;  // bytes of one map (it is copied into LDS)
 namespace {
 struct EjMaps {
@@ -1777,8 +1778,8 @@ bool ejmaps_prepare(int k) {
             row[c] = (uint8_t)host_rank(dev::squeeze2(R | (1u << cv), cu, cw));
           }
         }
-    uint32_t *d = nullptr;
-    if (hipMalloc(&d, bytes) != hipSuccess) return false;
+    uint32_t *d = (uint32_t *)table_pool_alloc(bytes);
+    if (!d) return false;
     if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
     M.d[ra] = d;
     M.words[ra] = (int)(bytes / 4);
@@ -1848,8 +1849,8 @@ static bool njmaps_build(int dev, int k) {  // ejm_mu held
           if (S == 0) break;
         }
       }
-      uint32_t *d = nullptr;
-      if (hipMalloc(&d, h.size()) != hipSuccess) return false;
+      uint32_t *d = (uint32_t *)table_pool_alloc(h.size());
+      if (!d) return false;
       if (hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) return false;
       M.d[ro][rA] = d;
       M.words[ro][rA] = (int)(h.size() / 4);

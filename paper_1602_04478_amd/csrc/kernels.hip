@@ -175,7 +175,7 @@ inline int grid_for(int64_t entries, int P) {
 }  // namespace
 
 
-// colex rank / unrank tables (per device, built once)
+// colex rank / unrank tables (per device, built once, in the constant-table pool)
 const uint16_t *lut_device(int device) {
   static std::mutex mu;
   static std::vector<uint16_t *> tabs;
@@ -205,8 +205,8 @@ const uint16_t *lut_device(int device) {
     std::sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) { return h[a] < h[b]; });
     for (uint32_t m : v) h[LUT_UNRANK + off++] = (uint16_t)m;
   }
-  uint16_t *d = nullptr;
-  if (hipMalloc(&d, sizeof(uint16_t) * LUT_SIZE) != hipSuccess) return nullptr;
+  uint16_t *d = (uint16_t *)table_pool_alloc(sizeof(uint16_t) * LUT_SIZE);
+  if (!d) return nullptr;
   if (hipMemcpy(d, h.data(), sizeof(uint16_t) * LUT_SIZE, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
   tabs[device] = d;
   return d;
