@@ -199,6 +199,22 @@ def disjoint_union(a: Graph, b: Graph) -> Graph:
     return from_edges(a.n + b.n, e, name=f"{a.name}+{b.name}")
 
 
+def hub_and_clique(leaves: int, clique: int = 12):
+    """A star (vertex 0 with `leaves` leaves 1..leaves) beside a clique on the
+    next `clique` vertices, with a fixed colouring for k = clique - 1 colours:
+    the hub colour 0, leaf i colour 1 + (i - 1) % (k - 1), clique vertex j
+    colour j % k (colour 0 twice).  Returns (graph, colours)."""
+    k = clique - 1
+    e = [(0, i) for i in range(1, leaves + 1)]
+    base = leaves + 1
+    e += [(base + a, base + b) for a in range(clique) for b in range(a + 1, clique)]
+    n = base + clique
+    col = np.zeros(n, dtype=np.uint8)
+    col[1:base] = [1 + (i - 1) % (k - 1) for i in range(1, base)]
+    col[base:] = [j % k for j in range(clique)]
+    return from_edges(n, np.array(e, dtype=np.int64), name=f"hub{leaves}+K{clique}"), col
+
+
 # The benchmark workloads, by name.  Sizes follow the configurations the
 # counting benchmark is quoted on; each is seeded and deterministic.
 def workload_graph(name: str) -> Graph:

@@ -61,6 +61,15 @@ def k33():
     return 6, [(a, b) for a in range(3) for b in range(3, 6)]
 
 
+def star_triangle(leaves: int = 8):
+    """A star of `leaves` leaves whose centre (node 0) also lies on a
+    triangle (nodes 0, leaves + 1, leaves + 2): k = leaves + 3."""
+    k = leaves + 3
+    E = [(0, i) for i in range(1, leaves + 1)]
+    E += [(0, leaves + 1), (leaves + 1, leaves + 2), (leaves + 2, 0)]
+    return k, E
+
+
 def random_query(rng: np.random.Generator, kmin: int = 4, kmax: int = 10):
     """One treewidth <= 2 query; family uniform over four shapes."""
     k = int(rng.integers(kmin, kmax + 1))

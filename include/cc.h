@@ -49,7 +49,7 @@ typedef enum {
   CC_E_QUERY_TW = 3,           /* no decomposition into blocks: the query has treewidth > 2 (Lemma 4.1) */
   CC_E_QUERY_DISCONNECTED = 4, /* the query is not connected */
   CC_E_K_RANGE = 5,            /* k < 2 or k > 12 */
-  CC_E_UNSUPPORTED = 6,        /* every decomposition needs a pair-keyed table (two non-adjacent boundary nodes) */
+  CC_E_UNSUPPORTED = 6,        /* a plan the library cannot run (tables wider than one workgroup's row) */
   CC_E_NOMEM = 7,              /* the work does not fit the device memory budget */
   CC_E_DEVICE = 8,             /* a HIP runtime call failed */
   CC_E_BUSY = 9                /* a server's request table is full */
@@ -103,11 +103,43 @@ cc_status cc_graph_info(cc_graph g, int64_t *n, int64_t *m, int64_t *max_degree)
  * `edges` (host, int32[2*num_edges]).  The query must be simple and connected
  * with 2 <= k <= 12.  The planner enumerates decomposition trees (Section 4.1,
  * Cases 1-3) and picks one by the heuristic of Section 6 (shortest longest
- * cycle, then fewest boundary nodes, then fewest annotations), among the trees
- * whose two-boundary blocks have adjacent boundary nodes.
- * Errors: CC_E_ARG, CC_E_K_RANGE, CC_E_QUERY_DISCONNECTED, CC_E_QUERY_TW, CC_E_UNSUPPORTED.
+ * cycle, then fewest boundary nodes, then fewest annotations), preferring trees
+ * whose two-boundary blocks have adjacent boundary nodes.  A block whose two
+ * boundary nodes are not adjacent (Configuration (B) of Section 5.1: K_{2,3},
+ * theta graphs, the worked example of Section 4.1) produces a table keyed by
+ * pairs of vertices that need not be adjacent in the data graph; it is
+ * computed by splitting its cycle at the two boundary nodes (the paper's
+ * path-splitting procedure, Procedures 1-2 of Section 5.1) and stored as a
+ * graph of its own over the nonzero pairs; a count whose pair table does not
+ * fit the device memory fails with CC_E_NOMEM.
+ * Errors: CC_E_ARG, CC_E_K_RANGE, CC_E_QUERY_DISCONNECTED, CC_E_QUERY_TW.
  */
 cc_status cc_query_create(int32_t k, int32_t num_edges, const int32_t *edges, cc_query *out);
+
+/* Flags for cc_query_create_ex. */
+#define CC_QUERY_PATH_SPLITTING 1u /* the baseline: every cycle split at its boundary nodes, no degree order */
+
+/*
+ * cc_query_create with choices:
+ *   flags  0: the degree-based procedure (Section 5.1, DB) for every block
+ *          whose boundary nodes allow it; CC_QUERY_PATH_SPLITTING: the
+ *          path-splitting baseline of Section 5.1 (PS, equivalent to the
+ *          colour-coding procedure of Alon et al.) for every cycle block --
+ *          the cycle is split at its boundary nodes (a root cycle at its first
+ *          node and the node opposite), the two paths start at the first
+ *          boundary node's image and take any vertex (no degree-order
+ *          filter), and every match is counted once.  Same counts as DB.
+ *   tree   -1: the heuristic's tree; else the index of a tree in the
+ *          planner's enumeration (0 .. num_trees - 1, see cc_query_tree_info),
+ *          e.g. to time every tree of a query (Section 8: the choice of tree).
+ * Errors: as cc_query_create; CC_E_ARG for an unknown flag or tree index.
+ */
+cc_status cc_query_create_ex(int32_t k, int32_t num_edges, const int32_t *edges, uint32_t flags, int32_t tree,
+                             cc_query *out);
+/* The chosen tree's index, the number of distinct trees enumerated (at most
+ * 4096 are kept), and the number of pair-keyed blocks in the chosen tree.
+ * Any output may be NULL. */
+cc_status cc_query_tree_info(cc_query q, int32_t *tree, int32_t *num_trees, int32_t *pair_keyed_blocks);
 cc_status cc_query_destroy(cc_query q);
 /* aut(Q) (Preliminaries), the number of blocks and the longest cycle of the chosen tree. */
 cc_status cc_query_info(cc_query q, uint64_t *aut, int32_t *num_blocks, int32_t *longest_cycle);
@@ -222,6 +254,26 @@ typedef struct {
   int32_t tried_dense_sources[8];
 } cc_tune_report;
 cc_status cc_last_tune_report(cc_tune_report *out);
+
+/*
+ * How the calling thread's last counting call (cc_count, cc_count_colors,
+ * cc_count_static, or the last query of cc_count_batch) split the sources of
+ * the root block -- the vertices that can be the highest vertex of a cycle
+ * match (at least two lower neighbours, Section 5.1) -- over the execution
+ * tiers: dense groups (the sources with the widest reach, a row for every
+ * lower vertex), the one-workgroup-per-source tier, and the sources that tier
+ * handed back to grouped launches (their frontier did not fit).  Also the
+ * colourings per trial group and the sources per group.
+ */
+typedef struct {
+  int64_t sources;
+  int64_t dense_sources;
+  int64_t light_sources;
+  int64_t handed_back;
+  int32_t trial_group;
+  int32_t group_sources;
+} cc_solve_stats;
+cc_status cc_last_solve_stats(cc_solve_stats *out);
 
 /* ------------------------------------------------------------------ serving */
 

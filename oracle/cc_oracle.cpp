@@ -866,6 +866,39 @@ int orc_db(int64_t n, const int64_t *rp, const int32_t *col, const uint8_t *colo
   }
 }
 
+// O3 with the width check of 64-bit tables (the paper fixes no counter
+// width; the reading used here: table entries are 64-bit and overflow is
+// flagged, never wrapped).  out[0..1] = the exact count (u128), out[2] = 1
+// when some entry of a child block's table -- a count of colourful matches
+// of the block's subquery keyed by its boundary images (Section 4.3) -- does
+// not fit in 64 bits.  The oracle's path tables and partial sums are not
+// checked: they depend on its own tie-break and decomposition.
+int orc_db_flagged(int64_t n, const int64_t *rp, const int32_t *col, const uint8_t *colours, int k, int ne,
+                   const int32_t *qe, int reverse_ties, u64 *out) {
+  try {
+    Query q = make_query(k, ne, qe);
+    Ctx c;
+    setup(c, n, rp, col, colours, k, q, reverse_ties);
+    solve_non_root(c);
+    const u128 lim = (u128)1 << 64;
+    bool wide = false;
+    for (size_t bi = 0; bi < c.plan.blocks.size(); bi++) {
+      for (auto &row : c.unary[bi])
+        for (auto &z : row) wide |= z.second >= lim;
+      for (auto &kv : c.binary[bi])
+        for (auto &z : kv.second) wide |= z.second >= lim;
+    }
+    std::vector<int64_t> src(n);
+    for (int64_t i = 0; i < n; i++) src[i] = i;
+    std::vector<u128> ps(src.size(), 0);
+    put128(root_count(c, src, ps.data()), out);
+    out[2] = wide ? 1 : 0;
+    return 0;
+  } catch (std::exception &) {
+    return -1;
+  }
+}
+
 int orc_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -68,6 +68,9 @@ def lib():
         L.orc_db.restype = ctypes.c_int
         L.orc_db.argtypes = [ctypes.c_int64, i64p, i32p, u8p, ctypes.c_int, ctypes.c_int, i32p,
                              ctypes.c_int, i64p, ctypes.c_int64, u64p, u64p]
+        L.orc_db_flagged.restype = ctypes.c_int
+        L.orc_db_flagged.argtypes = [ctypes.c_int64, i64p, i32p, u8p, ctypes.c_int, ctypes.c_int, i32p,
+                                     ctypes.c_int, u64p]
         L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -144,6 +147,21 @@ def db(g, k: int, edges, chi: np.ndarray, reverse_ties: bool = True, sources=Non
         raise ValueError("oracle DB rejected the query")
     vals = [int(per[2 * i]) | (int(per[2 * i + 1]) << 64) for i in range(src.size)]
     return _u128(out), vals
+
+
+def db_flagged(g, k: int, edges, chi: np.ndarray, reverse_ties: bool = True):
+    """The DB count with the 64-bit width check of the tables: returns
+    (exact count, flag), flag = some entry of a child block's table (colourful
+    matches of the block's subquery keyed by its boundary images) does not fit
+    in 64 bits."""
+    qe = _qe(edges)
+    out = np.zeros(3, dtype=np.uint64)
+    rc = lib().orc_db_flagged(g.n, _p(g.row_ptr, ctypes.c_int64), _p(g.col, ctypes.c_int32),
+                              _p(chi, ctypes.c_uint8), k, qe.shape[0], _p(qe, ctypes.c_int32),
+                              int(reverse_ties), _p(out, ctypes.c_uint64))
+    if rc != 0:
+        raise ValueError("oracle DB rejected the query")
+    return _u128(out), bool(out[2])
 
 
 def plan(k: int, edges, order=None):

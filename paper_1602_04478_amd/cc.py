@@ -13,15 +13,17 @@ LIB_PATH = os.path.join(_HERE, "libcc.so")
 
 CC_GRAPH_CLEAN = 1
 CC_GRAPH_REVERSE_TIES = 2
+CC_QUERY_PATH_SPLITTING = 1
 
 STATUS = {0: "CC_OK", 1: "CC_E_ARG", 2: "CC_E_GRAPH", 3: "CC_E_QUERY_TW", 4: "CC_E_QUERY_DISCONNECTED",
           5: "CC_E_K_RANGE", 6: "CC_E_UNSUPPORTED", 7: "CC_E_NOMEM", 8: "CC_E_DEVICE", 9: "CC_E_BUSY"}
 
 # every entry point declared in include/cc.h
-EXPORTS = ["cc_graph_create", "cc_graph_destroy", "cc_graph_info", "cc_query_create", "cc_query_destroy",
+EXPORTS = ["cc_graph_create", "cc_graph_destroy", "cc_graph_info", "cc_query_create", "cc_query_create_ex",
+           "cc_query_tree_info", "cc_query_destroy",
            "cc_query_info", "cc_query_plan", "cc_footprint", "cc_colors", "cc_count", "cc_count_static", "cc_count_colors",
            "cc_count_batch", "cc_server_create", "cc_server_add_graph", "cc_server_submit", "cc_server_poll",
-           "cc_server_drain", "cc_server_destroy", "cc_last_tune_report", "cc_profile_enable", "cc_profile_read", "cc_probe_copy",
+           "cc_server_drain", "cc_server_destroy", "cc_last_tune_report", "cc_last_solve_stats", "cc_profile_enable", "cc_profile_read", "cc_probe_copy",
            "cc_status_str", "cc_last_error"]
 
 
@@ -65,6 +67,8 @@ def lib():
         "cc_graph_destroy": [vp],
         "cc_graph_info": [vp, P(i64), P(i64), P(i64)],
         "cc_query_create": [i32, i32, vp, P(vp)],
+        "cc_query_create_ex": [i32, i32, vp, ctypes.c_uint32, i32, P(vp)],
+        "cc_query_tree_info": [vp, P(i32), P(i32), P(i32)],
         "cc_query_destroy": [vp],
         "cc_query_info": [vp, P(u64), P(i32), P(i32)],
         "cc_query_plan": [vp, vp, i32, P(i32)],
@@ -144,12 +148,21 @@ class Graph:
 class Query:
     """A planned query (cc_query_create)."""
 
-    def __init__(self, k: int, edges):
+    def __init__(self, k: int, edges, path_splitting: bool = False, tree: int = -1):
+        """path_splitting: the PS baseline for every cycle block
+        (cc_query_create_ex); tree: a tree index of the planner's
+        enumeration (-1: the heuristic's choice)."""
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         h = ctypes.c_void_p()
-        _check(lib().cc_query_create(k, e.shape[0], _ptr(e), ctypes.byref(h)))
+        flags = CC_QUERY_PATH_SPLITTING if path_splitting else 0
+        _check(lib().cc_query_create_ex(k, e.shape[0], _ptr(e), flags, tree, ctypes.byref(h)))
         self.h = h
         self.k = k
+
+    def tree_info(self):
+        t, nt, npk = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().cc_query_tree_info(self.h, ctypes.byref(t), ctypes.byref(nt), ctypes.byref(npk)))
+        return dict(tree=t.value, num_trees=nt.value, pair_keyed_blocks=npk.value)
 
     def info(self):
         a, nb, lc = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_int32()
@@ -276,6 +289,19 @@ def last_tune_report() -> dict:
     return {"trial_group": r.trial_group, "dense_sources": r.dense_sources, "graph_replays": int(r.graph_replays),
             "tried": [(r.tried_trial_group[i], r.tried_dense_sources[i], r.tried_seconds_per_colouring[i])
                       for i in range(n)]}
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("sources", ctypes.c_int64), ("dense_sources", ctypes.c_int64), ("light_sources", ctypes.c_int64),
+                ("handed_back", ctypes.c_int64), ("trial_group", ctypes.c_int32), ("group_sources", ctypes.c_int32)]
+
+
+def last_solve_stats() -> dict:
+    """How the calling thread's last counting call split the root block's
+    sources over the tiers (cc_last_solve_stats)."""
+    r = SolveStats()
+    _check(lib().cc_last_solve_stats(ctypes.byref(r)))
+    return {f: int(getattr(r, f)) for f, _ in SolveStats._fields_}
 
 
 class Server:

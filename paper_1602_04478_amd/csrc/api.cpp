@@ -118,20 +118,39 @@ cc_status cc_graph_info(cc_graph g, int64_t *n, int64_t *m, int64_t *max_degree)
 }
 
 cc_status cc_query_create(int32_t k, int32_t num_edges, const int32_t *edges, cc_query *out) {
+  return cc_query_create_ex(k, num_edges, edges, 0u, -1, out);
+}
+
+cc_status cc_query_create_ex(int32_t k, int32_t num_edges, const int32_t *edges, uint32_t flags, int32_t tree,
+                             cc_query *out) {
   return guard([&] {
     if (!out) cc::fail(CC_E_ARG, "null output handle");
     if (num_edges < 0 || (num_edges > 0 && !edges)) cc::fail(CC_E_ARG, "bad edge list");
+    if (flags & ~(uint32_t)CC_QUERY_PATH_SPLITTING) cc::fail(CC_E_ARG, "unknown query flag");
     std::vector<std::pair<int, int>> e;
     for (int i = 0; i < num_edges; i++) e.push_back({edges[2 * i], edges[2 * i + 1]});
     auto q = new cc_query_s;
     try {
-      q->plan = cc::make_plan(k, e);
+      q->plan = cc::make_plan(k, e, (flags & CC_QUERY_PATH_SPLITTING) ? cc::PLAN_PS : cc::PLAN_DB, tree);
       if (const char *vb = getenv("CC_VERBOSE"); vb && *vb == '1') cc::dump_programs(q->plan);
     } catch (...) {
       delete q;
       throw;
     }
     *out = q;
+  });
+}
+
+cc_status cc_query_tree_info(cc_query q, int32_t *tree, int32_t *num_trees, int32_t *pair_keyed_blocks) {
+  return guard([&] {
+    if (!q) cc::fail(CC_E_ARG, "null query");
+    if (tree) *tree = q->plan.tree;
+    if (num_trees) *num_trees = q->plan.num_trees;
+    if (pair_keyed_blocks) {
+      int c = 0;
+      for (auto &B : q->plan.blocks) c += B.pair_keyed ? 1 : 0;
+      *pair_keyed_blocks = c;
+    }
   });
 }
 
@@ -260,6 +279,19 @@ cc_status cc_last_tune_report(cc_tune_report *out) {
     out->graph_replays = r.replays;
     out->dense_sources = r.dense_sources;
     for (int i = 0; i < 8; i++) out->tried_dense_sources[i] = r.tried_dense[i];
+  });
+}
+
+cc_status cc_last_solve_stats(cc_solve_stats *out) {
+  return guard([&] {
+    if (!out) cc::fail(CC_E_ARG, "null output");
+    cc::SolveStats s = cc::last_solve_stats();
+    out->sources = s.sources;
+    out->dense_sources = s.dense;
+    out->light_sources = s.light;
+    out->handed_back = s.handed_back;
+    out->trial_group = s.trial_group;
+    out->group_sources = s.group_sources;
   });
 }
 

@@ -47,6 +47,16 @@ struct PBlock {
   std::vector<int> boundary;        // ordered boundary nodes (first, second)
   int size = 0;                     // |SQ(B)|: number of query nodes in the subquery
   int single_child = -1;            // BK_ROOT_SINGLE: the block annotating the last node
+  // Path splitting (Section 5.1, the baseline procedure): the cycle is split
+  // at its boundary nodes (the root at a_0 and the node opposite), the paths
+  // run from the image of the first boundary node with no degree-order
+  // filter, and every match is counted once.  Used for every block of a
+  // path-splitting plan, and in degree-based plans for the blocks whose two
+  // boundary nodes are not adjacent (their table is keyed by vertex pairs).
+  bool ps = false;
+  // the table is keyed by pairs of vertices that need not be adjacent: two
+  // boundary nodes not adjacent on the cycle
+  bool pair_keyed = false;
 };
 
 struct Op {
@@ -69,8 +79,15 @@ struct Program {
   int max_depth = 0;
 };
 
+// Plan modes: the degree-based program (Section 5.1, DB) or the path-splitting
+// baseline for every block.
+enum PlanMode { PLAN_DB = 0, PLAN_PS = 1 };
+
 struct Plan {
   int k = 0;
+  int mode = PLAN_DB;
+  int tree = -1;                 // index of the chosen tree among the enumerated ones
+  int num_trees = 0;             // distinct decomposition trees enumerated
   std::vector<std::pair<int, int>> edges;
   std::vector<PBlock> blocks;    // children before parents; the root is last
   std::vector<Program> programs; // per block (cycles only)
@@ -80,8 +97,10 @@ struct Plan {
   int num_annotations = 0;
 };
 
-// Build the plan; throws Error (via fail) on invalid or unsupported queries.
-Plan make_plan(int k, const std::vector<std::pair<int, int>> &edges);
+// Build the plan; throws Error (via fail) on invalid queries.  tree < 0:
+// the tree the heuristic of Section 6 picks; else the tree of that index in
+// the planner's enumeration order (CC_E_ARG when there is no such tree).
+Plan make_plan(int k, const std::vector<std::pair<int, int>> &edges, int mode = PLAN_DB, int tree = -1);
 // Flatten the tree for cc_query_plan.
 std::vector<int32_t> describe_plan(const Plan &p);
 
@@ -107,6 +126,7 @@ struct DevGraph {
   std::vector<int32_t> h_orig;      // rank -> original id
   std::vector<int32_t> h_rank;      // original id -> rank
   std::vector<int32_t> h_lowcnt;    // number of lower neighbours
+  std::vector<int32_t> h_deg;       // degree
   std::vector<int64_t> h_r2;        // two-step high-start reach estimate per source
   // hub schedule of the dense EdgeJoin: the vertices of degree > 2 * split_chunk
   // (ranks >= split_lo) as (vertex, neighbour offset) chunks, vertex descending
@@ -120,6 +140,7 @@ struct DevGraph {
   int64_t *rev = nullptr;
   int32_t *orig = nullptr;
   int32_t *lowcnt = nullptr;
+  int32_t *deg = nullptr;
   int device = 0;
   // items of the hub schedule usable below n_lim: a suffix of the list
   void split_range(int64_t n_lim, const int32_t **items, int *count) const;
@@ -176,6 +197,14 @@ struct TuneReport {
 CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t seed, const ExecOptions *tuning,
                         hipStream_t stream);
 TuneReport last_tune();  // of the calling thread's last run_batched
+
+// How the calling thread's last solve (any counting call) split its sources
+// over the tiers, for the root block (the last cycle block of the plan).
+struct SolveStats {
+  int64_t sources = 0, dense = 0, light = 0, handed_back = 0;
+  int trial_group = 0, group_sources = 0;
+};
+SolveStats last_solve_stats();
 
 // Device colouring (rank order) for one trial, copied to host by original id.
 void colours_to_host(const DevGraph &g, int k, uint64_t seed, int trial, uint8_t *out, hipStream_t stream);

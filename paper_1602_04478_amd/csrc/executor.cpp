@@ -194,7 +194,7 @@ uint64_t table_bytes(const DevGraph &g, const Plan &p, int T) {
   uint64_t b = 0;
   for (size_t i = 0; i < p.blocks.size(); i++) {
     const PBlock &B = p.blocks[i];
-    if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE) continue;
+    if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE || B.pair_keyed) continue;
     uint64_t keys = is_edge_table(p, (int)i) ? (uint64_t)g.m2 : (uint64_t)g.n;
     b += keys * (uint64_t)T * table_C(p, (int)i) * 8;
   }
@@ -509,7 +509,7 @@ static std::vector<Step> schedule(const Program &P, int k) {
   const int n = (int)P.ops.size();
   auto reads = [&](const Op &o, int r) {
     if (o.a == r || (o.kind == OP_MROOT || o.kind == OP_MU || o.kind == OP_MV || o.kind == OP_MEDGE ||
-                     o.kind == OP_MEDGE_T) && o.b == r)
+                     o.kind == OP_MEDGE_T || o.kind == OP_MPAIR) && o.b == r)
       return true;
     return o.kind == OP_AXPY && !o.first && o.dst == r;
   };
@@ -662,6 +662,22 @@ class Solver {
   void run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountResult &res, std::vector<u128> *per_source);
   int T() const { return z_.T; }
   int64_t ndense() const { return ndense_; }
+  SolveStats stats() const {
+    SolveStats s;
+    s.sources = (int64_t)sources_.size();
+    s.dense = ndense_;
+    s.trial_group = z_.T;
+    s.group_sources = z_.B_dense;
+    for (size_t bi = 0; bi < p_.blocks.size(); bi++) {
+      if (p_.blocks[bi].kind != BK_CYCLE && p_.blocks[bi].kind != BK_ROOT_CYCLE) continue;
+      s.sources = (int64_t)bx_[bi].src.size();
+      s.dense = bx_[bi].ndense;
+      const Light &L = light2_[bi].large ? light2_[bi] : light_[bi];
+      s.light = (int64_t)(light_[bi].src.size() + (light2_[bi].large ? light2_[bi].src.size() : 0));
+      s.handed_back = (int64_t)L.fails.size();
+    }
+    return s;
+  }
   uint64_t graph_replays = 0;
 
  private:
@@ -680,10 +696,56 @@ class Solver {
     LightArgs la{};
     int grid = 0;
   };
+  // How a cycle block runs its sources.  Degree-based blocks share the
+  // library's sources (at least two lower neighbours) and dense cut.  A
+  // path-splitting block (filter off) takes every vertex with a neighbour as
+  // a source.  A block that reads a pair-keyed table (an edge of its cycle is
+  // annotated by a block whose two boundary nodes are not adjacent) walks
+  // that table's graph and runs every vertex in dense groups, as does the
+  // pair-keyed block itself.
+  struct BlockExec {
+    bool nofilter = false, all_dense = false;
+    std::vector<int32_t> src;  // descending rank
+    int64_t ndense = 0;
+    DevMem d_src;
+  };
+  // A pair-keyed table: its entries (u, v) are listed by the merges, then
+  // laid out as a graph H of its own (symmetric CSR over the pairs, rows
+  // sorted, reverse slots) whose slots the table's rows are aligned to, as
+  // edge tables are aligned to the data graph's slots.  Rebuilt per trial
+  // group (the nonzero pairs depend on the colourings).
+  struct PairTab {
+    int64_t m2 = 0;
+    std::vector<int32_t> h_lowcnt, h_deg;
+    DevMem rp, col, rev, lowcnt, deg, idx;
+    DevMem keys, vals, cnt, stage_val, stage_mask;
+    uint64_t cap = 0;
+  };
   void run_light(Light &L, bool probe, int Tg, Profiler *prof);
   void enqueue(int Tg, bool seed_dev, bool probe, Profiler *prof);
   void enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof);
-  void run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof);
+  void run_group(size_t bi, const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof);
+  void finish_pairs(size_t bi, int Tg);
+  bool pair_tab(int tab) const { return tab >= 0 && p_.blocks[tab].pair_keyed; }
+  // the graph whose slots a child table is aligned to (the data graph, or a pair table's)
+  GraphDev graph_of(int tab) const {
+    if (!pair_tab(tab)) return gd_;
+    const PairTab &P = pt_[tab];
+    return GraphDev{P.rp.as<int64_t>(), P.col.as<int32_t>(), P.rev.as<int64_t>(), g_.n, P.m2};
+  }
+  // per vertex: the neighbours a walk may take first over that graph (lower
+  // ones, or all with the filter off), on the device and its maximum over a group
+  const int32_t *cnt_of(int tab, bool nofilter) const {
+    if (!pair_tab(tab)) return nofilter ? g_.deg : g_.lowcnt;
+    return nofilter ? pt_[tab].deg.as<int32_t>() : pt_[tab].lowcnt.as<int32_t>();
+  }
+  int max_cnt(int tab, bool nofilter, const Grp &G) const {
+    const std::vector<int32_t> &c =
+        !pair_tab(tab) ? (nofilter ? g_.h_deg : g_.h_lowcnt) : (nofilter ? pt_[tab].h_deg : pt_[tab].h_lowcnt);
+    int m = 0;
+    for (int64_t i = 0; i < G.B; i++) m = std::max(m, c[G.hsrc[i]]);
+    return m;
+  }
   TabDev tabdev(int blk) const {
     TabDev t{nullptr, 0, 0};
     if (blk >= 0) {
@@ -710,6 +772,9 @@ class Solver {
   GraphDev gd_{};
   std::vector<int32_t> sources_;
   int64_t ndense_ = 0;
+  std::vector<BlockExec> bx_;
+  std::vector<PairTab> pt_;
+  bool has_pairs_ = false;
   bool use_light_ = true, fallback_dense_ = false;
   int64_t light_scratch_ = 2 << 20;
   int64_t nlim_max_ = 1;
@@ -780,6 +845,61 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   d_src_.alloc(sizeof(int32_t) * std::max<size_t>(1, sources_.size()));
   if (!sources_.empty())
     HIP_CHECK(hipMemcpyAsync(d_src_.p, sources_.data(), sizeof(int32_t) * sources_.size(), hipMemcpyHostToDevice, st));
+  // per cycle block: which sources, which tiers, filter on or off
+  bx_.resize(p.blocks.size());
+  pt_.resize(p.blocks.size());
+  std::vector<int32_t> all_v, ps_src, ps_dense_order;
+  for (size_t bi = 0; bi < p.blocks.size(); bi++) {
+    const PBlock &B = p.blocks[bi];
+    BlockExec &X = bx_[bi];
+    if (B.kind != BK_CYCLE && B.kind != BK_ROOT_CYCLE) continue;
+    bool reads_pairs = false;
+    for (int c : B.edge_child) reads_pairs |= pair_tab(c);
+    X.nofilter = B.ps;
+    X.all_dense = reads_pairs || B.pair_keyed;
+    has_pairs_ |= B.pair_keyed;
+    if (X.all_dense) {
+      if (all_v.empty())
+        for (int64_t r = g.n - 1; r >= 0; r--) all_v.push_back((int32_t)r);
+      X.src = all_v;
+      X.ndense = (int64_t)X.src.size();
+    } else if (X.nofilter) {
+      // path splitting: every vertex with a neighbour may start the paths;
+      // dense groups for the sources whose unfiltered two-step reach would
+      // cost the sparse path more than one dense group (the degree-based
+      // cut with every edge of the graph below every source)
+      if (ps_src.empty()) {
+        std::vector<std::pair<int64_t, int32_t>> r2;
+        for (int64_t r = g.n - 1; r >= 0; r--) {
+          if (g.h_deg[r] < 1) continue;
+          int64_t reach = 0;
+          for (int64_t e = g.h_rp[r]; e < g.h_rp[r + 1]; e++) reach += g.h_deg[g.h_col[e]];
+          r2.push_back({reach, (int32_t)r});
+        }
+        std::stable_sort(r2.begin(), r2.end(), [](auto &a, auto &b2) { return a.first > b2.first; });
+        for (auto &x : r2) ps_src.push_back(x.second);
+        int64_t nd = 0;
+        for (size_t i = 0; i < r2.size(); i++) {
+          if (r2[i].first * 64 * 13 >= g.m2 && g.n > 4096) nd = (int64_t)i + 1;
+          else break;
+        }
+        if (const char *ev = getenv("CC_DENSE")) {
+          if (!strcmp(ev, "all")) nd = (int64_t)r2.size();
+          else if (!strcmp(ev, "none")) nd = 0;
+        }
+        ps_dense_order.assign(1, (int32_t)nd);
+      }
+      X.src = ps_src;
+      X.ndense = ps_dense_order[0];
+    } else {
+      X.src = sources_;
+      X.ndense = ndense_;
+    }
+    if (X.nofilter || X.all_dense) nlim_max_ = std::max<int64_t>(nlim_max_, g.n);
+    X.d_src.alloc(sizeof(int32_t) * std::max<size_t>(1, X.src.size()));
+    if (!X.src.empty())
+      HIP_CHECK(hipMemcpyAsync(X.d_src.p, X.src.data(), sizeof(int32_t) * X.src.size(), hipMemcpyHostToDevice, st));
+  }
   d_col_.alloc((size_t)g.n * T);
   d_sum_.alloc(sizeof(uint64_t) * 2 * 64);
   d_ovf_.alloc(sizeof(uint32_t) * 64);
@@ -791,7 +911,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   tabs_.resize(p.blocks.size());
   for (size_t i = 0; i < p.blocks.size(); i++) {
     const PBlock &B = p.blocks[i];
-    if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE) continue;
+    if (B.kind == BK_ROOT_CYCLE || B.kind == BK_ROOT_SINGLE || B.pair_keyed) continue;
     int64_t keys = is_edge_table(p, (int)i) ? g.m2 : g.n;
     tabs_[i].alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, keys) * T * table_C(p, (int)i));
   }
@@ -820,10 +940,27 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
     L.cnt.alloc(sizeof(uint32_t));
     L.bcnt.alloc(sizeof(uint32_t) * (size_t)level_chunks(nlim_max_));
   }
+  // pair-keyed blocks: the staging register of their merges and the entry
+  // list, whose capacity is what the memory left holds (with room for the
+  // table of twice as many slots that is laid out from it)
+  for (size_t bi = 0; bi < p.blocks.size(); bi++) {
+    if (!p.blocks[bi].pair_keyed) continue;
+    PairTab &Q = pt_[bi];
+    const int C = table_C(p, (int)bi);
+    Q.stage_val.alloc(sizeof(uint64_t) * (size_t)nlim_max_ * Bmax * T * C);
+    Q.stage_mask.alloc(sizeof(uint64_t) * (size_t)nlim_max_);
+    Q.cnt.alloc(sizeof(uint64_t));
+    const uint64_t row = 8 + 8 * (uint64_t)T * C;
+    const uint64_t left = opt.arena ? (uint64_t)(g_arena ? g_arena->size - g_arena->used : 0) / 2
+                                    : (uint64_t)(free_bytes() * 0.4);
+    Q.cap = std::min<uint64_t>(std::min<uint64_t>((uint64_t)g.n * (uint64_t)g.n, (uint64_t)1 << 26), left / (3 * row));
+    if (Q.cap < 1) fail(CC_E_NOMEM, "no memory left for the pair-keyed table");
+    Q.keys.alloc(sizeof(int32_t) * 2 * Q.cap);
+    Q.vals.alloc(sizeof(uint64_t) * (size_t)Q.cap * T * C);
+  }
   // one-workgroup tier per cycle block
   light_.resize(p.blocks.size());
   const int lgrid = light_grid(g.device);
-  std::vector<int32_t> rest(sources_.begin() + ndense_, sources_.end());
   for (size_t bi = 0; bi < p.blocks.size(); bi++) {
     const PBlock &B = p.blocks[bi];
     Light &L = light_[bi];
@@ -831,15 +968,17 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
       L.probed = true;
       continue;
     }
+    const BlockExec &X = bx_[bi];
+    std::vector<int32_t> rest(X.src.begin() + X.ndense, X.src.end());
     const Program &P = p.programs[bi];
-    const bool ok = use_light_ && !rest.empty() && P.max_depth <= light_max_depth() &&
+    const bool ok = use_light_ && !rest.empty() && !X.all_dense && P.max_depth <= light_max_depth() &&
                     (int)P.reg_s.size() <= light_max_regs();
     if (!ok) {
       L.probed = true;
-      L.fails = rest;
-      if (!rest.empty()) {
-        L.d_fails.alloc(4 * rest.size());
-        HIP_CHECK(hipMemcpyAsync(L.d_fails.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
+      L.fails = rest;  // copies are made from members, which outlive them
+      if (!L.fails.empty()) {
+        L.d_fails.alloc(4 * L.fails.size());
+        HIP_CHECK(hipMemcpyAsync(L.d_fails.p, L.fails.data(), 4 * L.fails.size(), hipMemcpyHostToDevice, st));
       }
       continue;
     }
@@ -869,11 +1008,13 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
     HIP_CHECK(hipMemcpyAsync(L.d_rC.p, rC.data(), 4 * rC.size(), hipMemcpyHostToDevice, st));
     HIP_CHECK(hipMemcpyAsync(L.d_rs.p, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st));
     HIP_CHECK(hipMemcpyAsync(L.d_tv.p, tv.data(), sizeof(TabDev) * tv.size(), hipMemcpyHostToDevice, st));
-    HIP_CHECK(hipMemcpyAsync(L.d_src.p, rest.data(), 4 * rest.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(L.d_src.p, L.src.data(), 4 * L.src.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));  // lops, rd, rC, rs and tv are local to this iteration
     L.grid = lgrid;
     LightArgs &la = L.la;
     la.g = gd_;
-    la.lowcnt = g.lowcnt;
+    la.nofilter = X.nofilter ? 1 : 0;
+    la.lowcnt = X.nofilter ? g.deg : g.lowcnt;
     la.colr = d_col_.as<uint8_t>();
     la.k = k;
     la.src = L.d_src.as<int32_t>();
@@ -948,8 +1089,9 @@ Solver::~Solver() {
   }
 }
 
-void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof) {
+void Solver::run_group(size_t bi, const Program &P, const Grp &G, int Tg, uint64_t *out, int C_out, Profiler *prof) {
   const int k = p_.k;
+  const BlockExec &X = bx_[bi];
   hipStream_t st = st_;
   const uint8_t *colr = d_col_.as<uint8_t>();
   uint32_t *ovf = d_ovf_.as<uint32_t>();
@@ -1000,6 +1142,8 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
   grp.k = k;
   grp.n_lim = G.hsrc[0];
   for (int64_t i = 1; i < G.B; i++) grp.n_lim = std::max<int64_t>(grp.n_lim, G.hsrc[i]);
+  grp.nofilter = X.nofilter ? 1 : 0;
+  if (X.nofilter) grp.n_lim = g_.n;  // paths may reach any vertex
   grp.dense = G.dense ? 1 : 0;
   grp.prof = nullptr;
   grp.hitems = nullptr;
@@ -1008,9 +1152,17 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
   grp.split_lo = g_.split_lo;
   if (G.dense) g_.split_range(grp.n_lim, &grp.hitems, &grp.nh);
   if (!grp.hitems) grp.nh = 0;
-  int max_low = 0;
-  for (int64_t i = 0; i < G.B; i++) max_low = std::max(max_low, g_.h_lowcnt[G.hsrc[i]]);
-  const int32_t *lowcnt_d = g_.lowcnt;
+  const int max_low = max_cnt(-1, X.nofilter, G);
+  const int32_t *lowcnt_d = cnt_of(-1, X.nofilter);
+  // an EdgeJoin over a pair table's graph has no hub schedule (that is the data graph's)
+  auto grp_for = [&](int tab) {
+    GroupDev g2 = grp;
+    if (pair_tab(tab)) {
+      g2.nh = 0;
+      g2.hitems = nullptr;
+    }
+    return g2;
+  };
   std::vector<char> built(P.max_depth + 2, 0);
   std::function<void(int)> build = [&](int d) {  // sparse groups: entries of depth d
     if (G.dense || built[d]) return;
@@ -1058,7 +1210,7 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
       continue;
     }
     static const char *names[] = {"init", "nodejoin", "edgejoin", "axpy", "merge_root",
-                                  "merge_u", "merge_v", "merge_edge", "merge_edge_t"};
+                                  "merge_u", "merge_v", "merge_edge", "merge_edge_t", "merge_pair"};
     if (op.kind == OP_INIT) build(1);
     if (op.kind == OP_EJ) build(P.reg_depth[op.dst]);
     grp.prof = nullptr;
@@ -1128,16 +1280,16 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
         // of the rows it marks, and every reader of a dense register reads a
         // row only when its activity bit is set
         if (G.dense) launch_fill_u64(d.mask, grp.n_lim, st);
-        launch_init(gd_, grp, lowcnt_d, max_low, colr, lv(op.dst), d, tabdev(op.tab), op.tab_src_first,
-                    tabdev(op.ntab), ovf, st);
+        launch_init(graph_of(op.tab), grp, cnt_of(op.tab, X.nofilter), max_cnt(op.tab, X.nofilter, G), colr,
+                    lv(op.dst), d, tabdev(op.tab), op.tab_src_first, tabdev(op.ntab), ovf, st);
         break;
       }
       case OP_NJ:
         launch_nj(gd_, grp, colr, lv(op.a), regdev(op.a), regdev(op.dst), tabdev(op.tab), ovf, st);
         break;
       case OP_EJ:
-        launch_ej(gd_, grp, colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst), tabdev(op.tab),
-                  op.tab_src_first, ovf, st);
+        launch_ej(graph_of(op.tab), grp_for(op.tab), colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst),
+                  tabdev(op.tab), op.tab_src_first, ovf, st);
         break;
       case OP_AXPY: {
         // a chain dst = w1 a1 + w2 a2 + ... in the next steps runs as one pass
@@ -1186,13 +1338,23 @@ void Solver::run_group(const Program &P, const Grp &G, int Tg, uint64_t *out, in
                       op.s, C_out, ovf, st);
         break;
       case OP_MEDGE:
-        launch_medge(gd_, grp, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), tabdev(op.tab),
+        launch_medge(graph_of(op.tab), grp, colr, lv(op.a), lv(op.b), regdev(op.a), regdev(op.b), tabdev(op.tab),
                      op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
         break;
       case OP_MEDGE_T:
-        launch_medge_t(gd_, grp, colr, lowcnt_d, max_low, tabdev(op.ntab), lv(op.b), regdev(op.b), tabdev(op.tab),
-                       op.tab_src_first, op.first, op.w, out, op.s, C_out, ovf, st);
+        launch_medge_t(graph_of(op.tab), grp, colr, cnt_of(op.tab, X.nofilter), max_cnt(op.tab, X.nofilter, G),
+                       tabdev(op.ntab), lv(op.b), regdev(op.b), tabdev(op.tab), op.tab_src_first, op.first, op.w,
+                       out, op.s, C_out, ovf, st);
         break;
+      case OP_MPAIR: {
+        if (!G.dense) fail(CC_E_DEVICE, "a pair-keyed merge runs in dense groups only");
+        PairTab &Q = pt_[bi];
+        RegDev stg{Q.stage_val.as<uint64_t>(), Q.stage_mask.as<uint64_t>(), (int)table_C(p_, (int)bi),
+                   p_.blocks[bi].size};
+        launch_mpair(grp, g_.n, colr, regdev(op.a), regdev(op.b), op.w, stg, Q.keys.as<int32_t>(),
+                     Q.vals.as<uint64_t>(), Q.cap, (unsigned long long *)Q.cnt.p, ovf, st);
+        break;
+      }
     }
     HIP_CHECK(hipGetLastError());
     if (prof) prof->end();
@@ -1220,7 +1382,7 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
                       8.0 * Tg * (n * tc(B.node_child[0]) + M * (tc(ec) + tc(B.node_child[1])) +
                                   n * table_C(p_, (int)bi)));
     }
-    launch_leaf(gd_, Tg, k, colr, tabdev(B.node_child[0]), tabdev(ec), ec >= 0 ? B.edge_first_lo[0] : 0,
+    launch_leaf(graph_of(ec), Tg, k, colr, tabdev(B.node_child[0]), tabdev(ec), ec >= 0 ? B.edge_first_lo[0] : 0,
                 tabdev(B.node_child[1]), tabs_[bi].as<uint64_t>(), B.size, table_C(p_, (int)bi), ovf, st);
     HIP_CHECK(hipGetLastError());
     if (prof) prof->end();
@@ -1235,19 +1397,22 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
   const Program &P = p_.programs[bi];
   uint64_t *out = nullptr;
   int C_out = 0;
-  if (B.kind == BK_CYCLE) {
+  const BlockExec &X = bx_[bi];
+  if (B.kind == BK_CYCLE && !B.pair_keyed) {
     out = tabs_[bi].as<uint64_t>();
     C_out = table_C(p_, (int)bi);
     int64_t keys = is_edge_table(p_, (int)bi) ? g_.m2 : g_.n;
     launch_fill_u64(out, keys * Tg * C_out, st);
   }
+  if (B.pair_keyed) launch_fill_u64(pt_[bi].cnt.as<uint64_t>(), 1, st);
   static const bool progress = [] {
     const char *v = getenv("CC_VERBOSE");
     return v && atoi(v) >= 2;
   }();
   // 1. dense groups: the sources with the widest reach
-  for (int64_t i = 0; i < ndense_; i += z_.B_dense) {
-    run_group(P, {d_src_.as<int32_t>() + i, sources_.data() + i, std::min<int64_t>(z_.B_dense, ndense_ - i), true}, Tg,
+  for (int64_t i = 0; i < X.ndense; i += z_.B_dense) {
+    run_group(bi, P,
+              {X.d_src.as<int32_t>() + i, X.src.data() + i, std::min<int64_t>(z_.B_dense, X.ndense - i), true}, Tg,
               out, C_out, prof);
     if (progress) fprintf(stderr, "[cc] block %zu: dense group at source %lld enqueued\n", bi, (long long)i), fflush(stderr);
   }
@@ -1269,7 +1434,7 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
   // 3. grouped path for what the one-workgroup tier does not take
   if (!LF.fails.empty()) {
     for (int64_t i = 0; i < (int64_t)LF.fails.size(); i += z_.B_sparse) {
-      run_group(P,
+      run_group(bi, P,
                 {LF.d_fails.as<int32_t>() + i, LF.fails.data() + i,
                  std::min<int64_t>(z_.B_sparse, (int64_t)LF.fails.size() - i), fallback_dense_},
                 Tg, out, C_out, prof);
@@ -1278,6 +1443,81 @@ void Solver::enqueue_block(size_t bi, int Tg, bool probe, Profiler *prof) {
                 LF.fails.size()), fflush(stderr);
     }
   }
+  if (B.pair_keyed) finish_pairs(bi, Tg);
+}
+
+// Lay out a pair-keyed block's entries as the graph H of its table (host:
+// sort the pairs of both orientations into rows, find each slot's entry and
+// reverse slot), then gather the entries' rows into slot order.  Needs the
+// entries on the host, so a solve with pair-keyed blocks synchronises here
+// (and is not captured in a graph).
+void Solver::finish_pairs(size_t bi, int Tg) {
+  PairTab &Q = pt_[bi];
+  hipStream_t st = st_;
+  const int C = table_C(p_, (int)bi);
+  const int64_t n = g_.n;
+  uint64_t cnt = 0;
+  HIP_CHECK(hipMemcpyAsync(&cnt, Q.cnt.p, sizeof(cnt), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (cnt > Q.cap)
+    fail(CC_E_NOMEM, "pair-keyed table of " + std::to_string(cnt) + " entries; memory for " + std::to_string(Q.cap));
+  std::vector<int32_t> keys(2 * cnt);
+  if (cnt) HIP_CHECK(hipMemcpy(keys.data(), Q.keys.p, sizeof(int32_t) * 2 * cnt, hipMemcpyDeviceToHost));
+  // entries sorted by (u, v), for the slot -> entry lookup
+  std::vector<int64_t> ent(cnt);
+  for (uint64_t i = 0; i < cnt; i++) ent[i] = (int64_t)i;
+  auto key = [&](int64_t i) { return ((int64_t)keys[2 * i] << 32) | (uint32_t)keys[2 * i + 1]; };
+  std::sort(ent.begin(), ent.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+  // arcs of both orientations, sorted and unique: the rows of H
+  std::vector<int64_t> arcs;
+  arcs.reserve(2 * cnt);
+  for (uint64_t i = 0; i < cnt; i++) {
+    const int64_t u = keys[2 * i], v = keys[2 * i + 1];
+    arcs.push_back((u << 32) | v);
+    arcs.push_back((v << 32) | u);
+  }
+  std::sort(arcs.begin(), arcs.end());
+  arcs.erase(std::unique(arcs.begin(), arcs.end()), arcs.end());
+  const int64_t m2 = (int64_t)arcs.size();
+  std::vector<int64_t> rp(n + 1, 0), rev(m2), idx(m2);
+  std::vector<int32_t> col(m2);
+  for (int64_t e = 0; e < m2; e++) {
+    rp[(arcs[e] >> 32) + 1]++;
+    col[e] = (int32_t)(arcs[e] & 0xffffffff);
+  }
+  for (int64_t x = 0; x < n; x++) rp[x + 1] += rp[x];
+  Q.h_lowcnt.assign(n, 0);
+  Q.h_deg.assign(n, 0);
+  for (int64_t x = 0; x < n; x++) {
+    const int32_t *r0 = col.data() + rp[x], *r1 = col.data() + rp[x + 1];
+    Q.h_deg[x] = (int32_t)(r1 - r0);
+    Q.h_lowcnt[x] = (int32_t)(std::lower_bound(r0, r1, (int32_t)x) - r0);
+  }
+  for (int64_t e = 0; e < m2; e++) {
+    const int64_t x = arcs[e] >> 32, y = col[e];
+    const int32_t *ry = col.data() + rp[y], *ry1 = col.data() + rp[y + 1];
+    rev[e] = rp[y] + (std::lower_bound(ry, ry1, (int32_t)x) - ry);
+    const int64_t want = (x << 32) | (uint32_t)y;
+    auto it = std::lower_bound(ent.begin(), ent.end(), want, [&](int64_t i, int64_t w) { return key(i) < w; });
+    idx[e] = (it != ent.end() && key(*it) == want) ? *it : -1;
+  }
+  Q.m2 = m2;
+  auto put = [&](DevMem &d, const void *h, size_t bytes) {
+    if (d.bytes < std::max<size_t>(bytes, 8)) d.alloc(std::max<size_t>(bytes, 8));
+    if (bytes) HIP_CHECK(hipMemcpyAsync(d.p, h, bytes, hipMemcpyHostToDevice, st));
+  };
+  put(Q.rp, rp.data(), sizeof(int64_t) * (n + 1));
+  put(Q.col, col.data(), sizeof(int32_t) * m2);
+  put(Q.rev, rev.data(), sizeof(int64_t) * m2);
+  put(Q.idx, idx.data(), sizeof(int64_t) * m2);
+  put(Q.lowcnt, Q.h_lowcnt.data(), sizeof(int32_t) * n);
+  put(Q.deg, Q.h_deg.data(), sizeof(int32_t) * n);
+  const size_t tb = sizeof(uint64_t) * (size_t)std::max<int64_t>(1, m2) * Tg * C;
+  if (tabs_[bi].bytes < tb) tabs_[bi].alloc(tb);
+  launch_pair_gather(Q.idx.as<int64_t>(), m2, Q.vals.as<uint64_t>(), (int64_t)Tg * C, tabs_[bi].as<uint64_t>(), st);
+  HIP_CHECK(hipGetLastError());
+  // the host vectors above are read by the copies: wait for them
+  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 void Solver::run_light(Light &L, bool probe, int Tg, Profiler *prof) {
@@ -1307,9 +1547,11 @@ void Solver::run_light(Light &L, bool probe, int Tg, Profiler *prof) {
     }
     L.src = keep;
     L.fails = f;
-    L.la.nsrc = (int)keep.size();
-    if (!keep.empty()) HIP_CHECK(hipMemcpyAsync(L.d_src.p, keep.data(), 4 * keep.size(), hipMemcpyHostToDevice, st));
-    if (!f.empty()) HIP_CHECK(hipMemcpyAsync(L.d_fails.p, f.data(), 4 * f.size(), hipMemcpyHostToDevice, st));
+    L.la.nsrc = (int)L.src.size();
+    if (!L.src.empty())
+      HIP_CHECK(hipMemcpyAsync(L.d_src.p, L.src.data(), 4 * L.src.size(), hipMemcpyHostToDevice, st));
+    if (!L.fails.empty())
+      HIP_CHECK(hipMemcpyAsync(L.d_fails.p, L.fails.data(), 4 * L.fails.size(), hipMemcpyHostToDevice, st));
     L.probed = true;
   }
 }
@@ -1347,7 +1589,7 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
     launch_permute_colours(d_hcol_.as<uint8_t>(), g_.orig, g_.n, Tg, d_col_.as<uint8_t>(), st);
   }
   Profiler prof(st, !opt_.arena);
-  const bool graphs = opt_.use_graphs && probed && cs.from_seed && !per_source && !prof.on;
+  const bool graphs = opt_.use_graphs && probed && cs.from_seed && !per_source && !prof.on && !has_pairs_;
   if (graphs) {
     if (!exec_ || exec_T_ != Tg) {
       if (exec_) (void)hipGraphExecDestroy(exec_);
@@ -1406,6 +1648,11 @@ void Solver::run_group_of_trials(int t0, int Tg, const ColourSource &cs, CountRe
 }
 
 // ------------------------------------------------------------------ main
+namespace {
+thread_local SolveStats g_last_stats;
+}
+SolveStats last_solve_stats() { return g_last_stats; }
+
 CountResult run_count(const DevGraph &g, const Plan &p, int trials, const ColourSource &cs, const ExecOptions &opt,
                       hipStream_t st, std::vector<u128> *per_source) {
   if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
@@ -1423,6 +1670,7 @@ CountResult run_count(const DevGraph &g, const Plan &p, int trials, const Colour
   res.overflow.assign(trials, 0);
   if (per_source) per_source->assign((size_t)trials * g.n, 0);
   for (int t0 = 0; t0 < trials; t0 += S.T()) S.run_group_of_trials(t0, std::min(S.T(), trials - t0), cs, res, per_source);
+  g_last_stats = S.stats();
   return res;
 }
 
@@ -1458,6 +1706,7 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
     rep.trial_group = S.T();
     rep.candidates = 0;
     rep.replays = S.graph_replays;
+    g_last_stats = S.stats();
     g_last_tune = rep;
     return res;
   }
@@ -1520,13 +1769,14 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
     rep.trial_group = best->T();
     rep.dense_sources = (int)best->ndense();
     rep.replays = best->graph_replays;
+    g_last_stats = best->stats();
   }
   g_last_tune = rep;
   return res;
 }
 
 void dump_programs(const Plan &p) {
-    static const char *kn[] = {"INIT", "NJ", "EJ", "AXPY", "MROOT", "MU", "MV", "MEDGE", "MEDGE_T"};
+    static const char *kn[] = {"INIT", "NJ", "EJ", "AXPY", "MROOT", "MU", "MV", "MEDGE", "MEDGE_T", "MPAIR"};
     for (size_t bi = 0; bi < p.programs.size(); bi++) {
       const Program &P = p.programs[bi];
       if (P.ops.empty()) continue;

@@ -21,6 +21,7 @@ DevGraph::~DevGraph() {
   if (rev) (void)hipFree(rev);
   if (orig) (void)hipFree(orig);
   if (lowcnt) (void)hipFree(lowcnt);
+  if (deg) (void)hipFree(deg);
   if (split_items) (void)hipFree(split_items);
 }
 
@@ -192,6 +193,9 @@ std::unique_ptr<DevGraph> make_graph(int64_t n, const int64_t *row_ptr, const in
   HIP_CHECK(hipMalloc(&G->rev, sizeof(int64_t) * std::max<int64_t>(1, G->m2)));
   HIP_CHECK(hipMalloc(&G->orig, sizeof(int32_t) * n));
   HIP_CHECK(hipMalloc(&G->lowcnt, sizeof(int32_t) * n));
+  HIP_CHECK(hipMalloc(&G->deg, sizeof(int32_t) * n));
+  G->h_deg.resize(n);
+  for (int64_t r = 0; r < n; r++) G->h_deg[r] = (int32_t)(G->h_rp[r + 1] - G->h_rp[r]);
   HIP_CHECK(hipMemcpyAsync(G->rp, G->h_rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, stream));
   if (G->m2) {
     HIP_CHECK(hipMemcpyAsync(G->col, G->h_col.data(), sizeof(int32_t) * G->m2, hipMemcpyHostToDevice, stream));
@@ -199,6 +203,7 @@ std::unique_ptr<DevGraph> make_graph(int64_t n, const int64_t *row_ptr, const in
   }
   HIP_CHECK(hipMemcpyAsync(G->orig, G->h_orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
   HIP_CHECK(hipMemcpyAsync(G->lowcnt, G->h_lowcnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipMemcpyAsync(G->deg, G->h_deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
   HIP_CHECK(hipStreamSynchronize(stream));
   return G;
 }

@@ -73,6 +73,11 @@ __device__ __forceinline__ int64_t row_of(const GroupDev &g, const LevelDev &L, 
 __device__ __forceinline__ bool live(const GroupDev &g, const RegDev &r, int64_t v, int b) {
   return !g.dense || ((r.mask[v] >> b) & 1ull);
 }
+// Every later path vertex must lie below this bound: the source itself
+// (degree order, Section 5.1), or no bound at all when the group runs with
+// the filter off (path splitting: every vertex may follow).
+constexpr int VBIG = 0x7fffffff;
+__device__ __forceinline__ int64_t vbound(const GroupDev &g, int64_t u) { return g.nofilter ? (int64_t)VBIG : u; }
 
 __device__ __forceinline__ void mark(uint64_t *m, int64_t v, int b) {
   const uint64_t bit = 1ull << b;
@@ -115,8 +120,8 @@ __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int
 // OR; below the smallest such u_b that is all of m.
 __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lout) {
   constexpr int TEAM = 16;
-  __shared__ int32_t s_u[64];
-  for (int i = threadIdx.x; i < 64; i += BLK) s_u[i] = i < grp.B ? grp.src[i] : 0;
+  __shared__ int32_t s_u[64];  // per source: the bound below which its walks continue
+  for (int i = threadIdx.x; i < 64; i += BLK) s_u[i] = i < grp.B ? (int32_t)vbound(grp, grp.src[i]) : 0;
   __syncthreads();
   const int teams = BLK / TEAM, team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
   uint64_t prd = 0, pwr = 0;  // profiling: bytes read, written
@@ -362,8 +367,8 @@ __global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uin
     int64_t w;
     int b;
     entry_vb(grp, Lout, e, w, b);
-    const int64_t u = grp.src[b];
-    if (w < u) {
+    const int64_t u = grp.src[b], ub = vbound(grp, u);
+    if (w < ub) {
       const int64_t r0 = g.rp[w], r1 = g.rp[w + 1];
       for (int t = 0; t < T; t++) {
         const int cu = colr[(int64_t)t * g.n + u], cw = colr[(int64_t)t * g.n + w];
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uin
           // gather
           const int64_t ee = j0 + lane;
           const int64_t v = ee < r1 ? g.col[ee] : INT64_MAX;
-          const bool in = v < u;
+          const bool in = v < ub;
           bool ok = false;
           int64_t id = -1;
           int cv = 0;
@@ -469,10 +474,11 @@ __global__ __launch_bounds__(WAVE) void k_ej(GraphDev g, GroupDev grp, const uin
       nz |= v != 0;
     }
     if (grp.dense) {
+      // the activity words were cleared before the launch (every bit of
+      // them, also the bits of sources this group does not have)
       const bool any = __any(nz);
       if (lane == 0) {
         if (any) atomicOr((unsigned long long *)&dst.mask[w], 1ull << b);
-        else atomicAnd((unsigned long long *)&dst.mask[w], ~(1ull << b));
         n_ent += any;
       }
     } else if (lane == 0) {
@@ -545,6 +551,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
   __shared__ uint16_t s_rank[2048];
   __shared__ uint32_t s_um[256];  // unranked slots: input (data edge) or output (annotated)
   __shared__ int32_t s_src[WAVE];
+  __shared__ int32_t s_bnd[WAVE];  // per source: its walks' bound (itself, or none with the filter off)
   __shared__ uint64_t s_live[EPI_MAX_REGS * (NB / SW)];  // dense: per written register and group, live rows
   extern __shared__ uint64_t accs[];  // [columns][64]: lane-owned columns, EdgeJoin output first
   int64_t *const s_rid = (int64_t *)(accs + (size_t)epi.ncols * NB);  // [regs][64] operands' rows
@@ -566,7 +573,10 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
   const int W = ANN ? C : Ca;
   const int lane = tid % WAVE;
   for (int c = tid; c < W; c += NB) s_um[c] = unrank(lut, ANN ? ro : ra, c);
-  if (tid < WAVE) s_src[tid] = tid < B ? grp.src[tid] : -1;
+  if (tid < WAVE) {
+    s_src[tid] = tid < B ? grp.src[tid] : -1;
+    s_bnd[tid] = tid < B ? (int32_t)vbound(grp, grp.src[tid]) : -1;
+  }
   uint32_t *const s_map = (uint32_t *)((char *)accs + ejv_lds(epi.ncols, epi.nregs, EPI, NB));
   if (MAP)
     for (int i = tid; i < emap_w; i += NB) s_map[i] = emap[i];
@@ -625,7 +635,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
     // output rows at w: dense -- every source above w; sparse -- the marks
     uint64_t ob = 0;
     if (grp.dense) {
-      for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_src[i + gl] > w) << i;
+      for (int i = 0; i < B; i += SW) ob |= gballot(i + gl < B && s_bnd[i + gl] > w) << i;
     } else {
       ob = Lout.mb[2 * (int64_t)w];
     }
@@ -647,7 +657,8 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
       rest &= ~pass;
       const int b = lb < np ? nth_set_bit(pass, lb) : -1;
       const int u = b >= 0 ? s_src[b] : 0;
-      int umax = u;  // the neighbours below the pass's largest source
+      const int ub = b >= 0 ? s_bnd[b] : 0;
+      int umax = ub;  // the neighbours below the pass's largest bound
       for (int o = SW / 2; o > 0; o >>= 1) umax = max(umax, __shfl_xor(umax, o, SW));
       int cu = 0, cw = 0;
       bool act = false;
@@ -681,7 +692,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
           // which b is not idle at w (its colour differs from w's)
           for (uint64_t r = inb; r; r &= r - 1) {
             const int uq = s_src[__builtin_ctzll(r)];
-            if (vj < uq)
+            if (vj < s_bnd[__builtin_ctzll(r)])
               for (int t = 0; t < T; t++) n_scan += colr[(int64_t)t * n + uq] != colr[(int64_t)t * n + w] ? 1u : 0u;
           }
         }
@@ -714,7 +725,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
             const int64_t bA = PD ? 0 : __shfl(bj, jl, SW);
             if (pp >= P) continue;
             const int bb = nth_set_bit(vm, kth);
-            if (vA >= s_src[bb]) continue;
+            if (vA >= s_bnd[bb]) continue;
             n_rows++;
             const uint64_t below_bb = (1ull << bb) - 1ull;
             const int colw = (tid - gl) + __popcll(pass & below_bb);  // the lane of source bb
@@ -746,7 +757,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
             const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA, SW);
             const int64_t bA = grp.dense ? 0 : __shfl(bj, jA, SW);
             int cA = __shfl(cvj, jA, SW);
-            bool okA = act && vA < u && ((ibA >> b) & 1ull);
+            bool okA = act && vA < ub && ((ibA >> b) & 1ull);
             if (T > 1 && okA) cA = colr[(int64_t)lt * n + vA];
             okA = okA && cA != cu && cA != cw;
             if (!okA) continue;
@@ -785,8 +796,8 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
             const uint64_t mfA = grp.dense ? 0 : __shfl(mfull, jA, SW), mfB = grp.dense ? 0 : __shfl(mfull, jB, SW);
             const int64_t bA = grp.dense ? 0 : __shfl(bj, jA, SW), bB = grp.dense ? 0 : __shfl(bj, jB, SW);
             int cA = __shfl(cvj, jA, SW), cB = __shfl(cvj, jB, SW);
-            bool okA = act && vA < u && ((ibA >> b) & 1ull);
-            bool okB = act && hasB && vB < u && ((ibB >> b) & 1ull);
+            bool okA = act && vA < ub && ((ibA >> b) & 1ull);
+            bool okB = act && hasB && vB < ub && ((ibB >> b) & 1ull);
             if (T > 1) {
               if (okA) cA = colr[(int64_t)lt * n + vA];
               if (okB) cB = colr[(int64_t)lt * n + vB];
@@ -839,7 +850,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
             const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj, SW);
             const int64_t vb = grp.dense ? 0 : __shfl(bj, jj, SW);
             const int cvs = __shfl(cvj, jj, SW);
-            if (!act || v >= u || !((ib >> b) & 1ull)) continue;
+            if (!act || v >= ub || !((ib >> b) & 1ull)) continue;
             const int cv = T == 1 ? cvs : colr[(int64_t)lt * n + v];
             if (cv == cu || cv == cw) continue;
             const int64_t id = grp.dense ? (int64_t)v * B + b : vb + __popcll(mf & ((1ull << b) - 1ull));
@@ -1049,7 +1060,7 @@ __global__ __launch_bounds__(BLK) void k_nj(GroupDev grp, int64_t n, const uint8
     const int64_t u = grp.src[b];
     uint64_t acc = 0;
     bool of = false;
-    if (v < u) {
+    if (v < vbound(grp, u)) {
       const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
       if (cu != cv) {
         if (c == 0) prd += 8 * (uint64_t)(Ca + nt.C);
@@ -1203,7 +1214,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
         const int64_t u = s_u[b];
         const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
         x = 0;
-        if (v < u && cu != cv) {
+        if (v < vbound(grp, u) && cu != cv) {
           if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
           if (tm.jmw[q]) {
             const int ns = tm.jns[q];
@@ -1277,8 +1288,9 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
   const int lane = threadIdx.x % 64;
   const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
   uint64_t ofm = 0, prd = 0, pwr = 0;
+  const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;  // the group's sources
   for (int64_t v = wave; v < grp.n_lim; v += nwave) {
-    const uint64_t m = a.mask[v];
+    const uint64_t m = a.mask[v] & bmask;
     prd += lane == 0 ? 8 : 0;
     if (!m) continue;
     const int items = __popcll(m) * per;
@@ -1289,7 +1301,7 @@ __global__ __launch_bounds__(BLK) void k_nj_dense(GroupDev grp, int64_t n, const
       const int64_t u = grp.src[b];
       uint64_t acc = 0;
       bool of = false;
-      if (v < u) {
+      if (v < vbound(grp, u)) {
         const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
         if (cu != cv) {
           if (c == 0) prd += 8 * (uint64_t)(Ca + nt.C);
@@ -1338,6 +1350,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
   const int lane = threadIdx.x % 64;
   const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
   uint64_t ofm = 0, prd = 0, pwr = 0;
+  const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;  // the group's sources
   for (int64_t v = wave; v < grp.n_lim; v += nwave) {
     uint64_t mt[4] = {0, 0, 0, 0};
     if (lane == 0) {
@@ -1348,7 +1361,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
 #pragma unroll
     for (int q = 0; q < 4; q++)
       if (q < tm.n) {
-        mt[q] = tm.a[q].mask[v];
+        mt[q] = tm.a[q].mask[v] & bmask;
         m |= mt[q];
       }
     if (lane == 0) dst.mask[v] = m;
@@ -1370,7 +1383,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
           const int64_t u = s_u[b];
           const int cu = s_cu[t * WAVE + b], cv = T == 1 ? cv1 : colr[(int64_t)t * n + v];
           x = 0;
-          if (v < u && cu != cv) {
+          if (v < vbound(grp, u) && cu != cv) {
             if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
             if (JM || tm.jmw[q]) {
               const int ns = tm.jns[q];
@@ -1498,7 +1511,7 @@ __global__ __launch_bounds__(BLK) void k_munary(GroupDev grp, int64_t n, const u
     int b;
     entry_vb(grp, La, e, v, b);
     const int64_t u = grp.src[b];
-    if (v >= u || !live(grp, a, v, b)) continue;
+    if (v >= vbound(grp, u) || !live(grp, a, v, b)) continue;
     const int64_t eb = row_of(grp, Lb, bb, v, b);
     if (eb < 0) continue;
     const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
@@ -1529,6 +1542,89 @@ __global__ __launch_bounds__(BLK) void k_munary(GroupDev grp, int64_t n, const u
   flag_trials(ovf, ofm);
 }
 
+// ------------------------------------------------------------------ pair-keyed merges
+// P[(u_b, v)][R'] = w * sum over splits R' = R1 + R2 of a[(v,b)][R1] * b[(v,b)][R2]
+// (Procedure 2 of Section 5.1: the two paths from u meet at v with colour
+// sets overlapping exactly in {chi u, chi v}; R', R1, R2 with those two
+// colours squeezed out).  Dense groups: one thread per (row, trial, output
+// slot) into a staging register (rows v * B + b) whose activity word marks
+// the nonzero rows.
+__global__ __launch_bounds__(BLK) void k_mpair(GroupDev grp, int64_t n, const uint8_t *colr, RegDev a, RegDev bb,
+                                               uint64_t w, RegDev dst, uint32_t *ovf, const uint16_t *lut) {
+  __shared__ uint16_t s_rank[2048];
+  load_rank(s_rank, lut);
+  const int T = grp.T, Ca = a.C, Cb = bb.C, C = dst.C;
+  const int ra = a.s - 2;
+  const int64_t per = (int64_t)T * C;
+  const int64_t N = grp.n_lim * (int64_t)grp.B * per;
+  uint64_t ofm = 0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
+    const int64_t row = i / per;
+    const int r = (int)(i - row * per), t = r / C, c = r - t * C;
+    const int64_t v = row / grp.B;
+    const int b = (int)(row - v * grp.B);
+    uint64_t sum = 0;
+    bool of = false;
+    const int64_t u = grp.src[b];
+    if (v != u && live(grp, a, v, b) && live(grp, bb, v, b)) {
+      const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
+      if (cu != cv) {
+        const uint32_t R = spread2(unrank(lut, dst.s - 2, c), cu, cv);
+        const uint64_t *ar = a.val + (row * T + t) * Ca;
+        const uint64_t *br = bb.val + (row * T + t) * Cb;
+        uint32_t s1 = R;
+        for (;;) {
+          if (__popc(s1) == ra) {
+            const uint64_t x = ar[s_rank[squeeze2(s1, cu, cv)]];
+            if (x) {
+              const uint64_t y = br[s_rank[squeeze2(R & ~s1, cu, cv)]];
+              if (y) add_ck(sum, mul_ck(x, y, of), of);
+            }
+          }
+          if (s1 == 0) break;
+          s1 = (s1 - 1) & R;
+        }
+        if (sum) sum = mul_ck(sum, w, of);
+      }
+    }
+    dst.val[i] = sum;
+    if (sum) atomicOr((unsigned long long *)&dst.mask[v], 1ull << b);
+    if (of) ofm |= 1ull << t;
+  }
+  flag_trials(ovf, ofm);
+}
+
+// Append the nonzero staged rows as pair-table entries: keys (u_b, v),
+// values [T][C].  Entries beyond `cap` are counted but not written.
+__global__ __launch_bounds__(BLK) void k_pair_emit(GroupDev grp, RegDev st, int32_t *keys, uint64_t *vals,
+                                                   uint64_t cap, unsigned long long *cnt) {
+  const int64_t per = (int64_t)grp.T * st.C;
+  const int64_t N = grp.n_lim * (int64_t)grp.B;
+  for (int64_t row = (int64_t)blockIdx.x * BLK + threadIdx.x; row < N; row += (int64_t)gridDim.x * BLK) {
+    const int64_t v = row / grp.B;
+    const int b = (int)(row - v * grp.B);
+    if (!((st.mask[v] >> b) & 1ull)) continue;
+    const unsigned long long pos = atomicAdd(cnt, 1ull);
+    if (pos >= cap) continue;
+    keys[2 * pos] = grp.src[b];
+    keys[2 * pos + 1] = (int32_t)v;
+    const uint64_t *sr = st.val + row * per;
+    uint64_t *dr = vals + (int64_t)pos * per;
+    for (int64_t q = 0; q < per; q++) dr[q] = sr[q];
+  }
+}
+
+// Table rows aligned to the slots of a pair table's graph: slot e takes
+// entry idx[e]'s row, or zeros (idx -1).
+__global__ void k_pair_gather(const int64_t *idx, int64_t m2, const uint64_t *vals, int64_t per, uint64_t *tab) {
+  const int64_t N = m2 * per;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / per;
+    const int64_t j = idx[e];
+    tab[i] = j >= 0 ? vals[j * per + (i - e * per)] : 0;
+  }
+}
+
 // ------------------------------------------------------------------ edge merges
 // T[x,y][R'] += w * a[(x,b)][R1] * E(x,y)[Re] * b[(y,b)][R2],  R' \ {chi u_b} = R1 + Re + R2
 __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev La,
@@ -1549,14 +1645,14 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
     int b;
     entry_vb(grp, La, e, x, b);
     const int64_t u = grp.src[b];
-    if (x >= u || !live(grp, a, x, b)) continue;
+    if (x >= vbound(grp, u) || !live(grp, a, x, b)) continue;
     const int cu = colr[(int64_t)t * g.n + u], cx = colr[(int64_t)t * g.n + x];
     if (cu == cx) continue;
     const uint64_t *ar = a.val + (e * T + t) * Ca;
     bool of = false;
     for (int64_t ee = g.rp[x]; ee < g.rp[x + 1]; ee++) {
       const int64_t y = g.col[ee];
-      if (y >= u) break;
+      if (y >= vbound(grp, u)) break;
       const int64_t eb = row_of(grp, Lb, bb, y, b);
       if (eb < 0) continue;
       const int cy = colr[(int64_t)t * g.n + y];
@@ -1960,6 +2056,9 @@ void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
   const int64_t N = grp.dense ? grp.n_lim * grp.B : (int64_t)1 << 62;
   const int gr = (int)std::max<int64_t>(1, std::min<int64_t>(N, 32768));
   const size_t lds = (size_t)2 * grp.T * dst.C * sizeof(uint64_t);
+  // dense: the kernel sets the activity bit of each live row (v, b); the
+  // words start at zero
+  if (grp.dense) launch_fill_u64(dst.mask, grp.n_lim, st);
   if (etab.val)
     hipLaunchKernelGGL(k_ej<true>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab, e_src_first,
                        ovf, cur_lut());
@@ -2044,6 +2143,23 @@ void launch_medge(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, L
                   int C_out, uint32_t *ovf, hipStream_t st) {
   hipLaunchKernelGGL(k_medge, dim3(fgrid(grp, (int64_t)grp.T * C_out)), dim3(BLK), 0, st, g, grp, colr, La, Lb, a, b,
                      etab, e_src_first, out_first_is_x, w, out, s_out, C_out, ovf, cur_lut());
+}
+
+void launch_mpair(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w, RegDev stage,
+                  int32_t *keys, uint64_t *vals, uint64_t cap, unsigned long long *cnt, uint32_t *ovf,
+                  hipStream_t st) {
+  launch_fill_u64(stage.mask, grp.n_lim, st);
+  hipLaunchKernelGGL(k_mpair, dim3(fgrid(grp, (int64_t)grp.T * stage.C)), dim3(BLK), 0, st, grp, n, colr, a, b, w,
+                     stage, ovf, cur_lut());
+  hipLaunchKernelGGL(k_pair_emit, dim3(fgrid(grp, 1)), dim3(BLK), 0, st, grp, stage, keys, vals, cap, cnt);
+}
+
+void launch_pair_gather(const int64_t *idx, int64_t m2, const uint64_t *vals, int64_t per, uint64_t *tab,
+                        hipStream_t st) {
+  const int64_t N = m2 * per;
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)std::min<int64_t>((N + BLK - 1) / BLK, 8192)), dim3(BLK), 0, st,
+                     idx, m2, vals, per, tab);
 }
 
 void launch_medge_t(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, const int32_t *lowcnt,

@@ -18,7 +18,8 @@ enum OpKind {
   OP_MU = 5,     // U[u]  += w * sum_v a[v] (x) b[v]
   OP_MV = 6,     // U[v]  += w * a[v] (x) b[v]
   OP_MEDGE = 7,  // T[x,y] += w * a[x] (x) E(x,y) (x) b[y]
-  OP_MEDGE_T = 8 // T[u,y] += w * A[u] (x) E(u,y) (x) b[y]   (or T[y,u] when swapped)
+  OP_MEDGE_T = 8, // T[u,y] += w * A[u] (x) E(u,y) (x) b[y]   (or T[y,u] when swapped)
+  OP_MPAIR = 9   // P[u,v] += w * a[v] (x) b[v]               (pair-keyed table, u the source)
 };
 
 // The entries of one path length (depth) for a group: the (vertex, source)
@@ -52,6 +53,7 @@ struct GroupDev {
   int k;
   int64_t n_lim;      // every frontier vertex is below this rank
   int dense;          // 1: domain = all (v, b) with v < n_lim; 0: the register's list
+  int nofilter;       // 1: path vertices are not required to lie below their source (path splitting)
   uint64_t *prof;     // optional work counters of the launch (profiling)
   // Dense EdgeJoin hub schedule: output vertices of rank >= split_lo (below
   // n_lim) have their neighbour lists cut into chunks of split_chunk
@@ -168,6 +170,15 @@ void launch_medge_t(const GraphDev &g, const GroupDev &grp, const uint8_t *colr,
                     int max_low, TabDev ntab, LevelDev Lb, RegDev b, TabDev etab, int e_src_first,
                     int out_first_is_u, uint64_t w, uint64_t *out, int s_out, int C_out, uint32_t *ovf,
                     hipStream_t st);
+// pair-keyed merge (dense groups): rows of P[(u_b, v)] staged in `stage`
+// (rows v * B + b, activity words), the nonzero ones appended to the entry
+// list (keys (u, v), values [T][C]) through the counter cnt (capacity cap)
+void launch_mpair(const GroupDev &grp, int64_t n, const uint8_t *colr, RegDev a, RegDev b, uint64_t w, RegDev stage,
+                  int32_t *keys, uint64_t *vals, uint64_t cap, unsigned long long *cnt, uint32_t *ovf,
+                  hipStream_t st);
+// table rows aligned to a pair graph's slots: slot e <- entry idx[e] (or zeros when -1)
+void launch_pair_gather(const int64_t *idx, int64_t m2, const uint64_t *vals, int64_t per, uint64_t *tab,
+                        hipStream_t st);
 void launch_leaf(const GraphDev &g, int T, int k, const uint8_t *colr, TabDev na, TabDev ea, int e_src_first,
                  TabDev nb, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
 void launch_root_single(int64_t n, int T, TabDev u, AccDev acc, hipStream_t st);
@@ -180,7 +191,8 @@ struct LOp {
 
 struct LightArgs {
   GraphDev g;
-  const int32_t *lowcnt;
+  const int32_t *lowcnt;  // lower neighbours per vertex (the degree with nofilter)
+  int nofilter;           // 1: path vertices need not lie below the source
   const uint8_t *colr;
   int T, k;
   const int32_t *src;   // candidate sources (ranks)

@@ -120,6 +120,8 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
     const int si = s_si;
     if (si >= A.nsrc) break;
     const int64_t u = A.src[si];
+    // later path vertices lie below u (degree order), or anywhere with the filter off
+    const int64_t ub = A.nofilter ? (int64_t)INT_MAX : u;
     // ------------------------------------------------ structure
     const int n1 = A.lowcnt[u];
     if (n1 > KPOOL) {
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
         int64_t v = s_k[i];
         for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
           int32_t w = g.col[e];
-          if (w >= u) break;
+          if (w >= ub) break;
           int pos = atomicAdd(&s_n, 1);
           if (pos < EMAX) s_c[pos] = w;
         }
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
         int c = 0;
         for (int64_t e = g.rp[w]; e < g.rp[w + 1]; e++) {
           int32_t v = g.col[e];
-          if (v >= u) break;
+          if (v >= ub) break;
           c += find_key(s_k + k0, k1 - k0, v) >= 0;
         }
         offs[wi] = c;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
         int pos = offs[wi];
         for (int64_t e = g.rp[w]; e < g.rp[w + 1]; e++) {
           int32_t v = g.col[e];
-          if (v >= u) break;
+          if (v >= ub) break;
           int q = find_key(s_k + k0, k1 - k0, v);
           if (q >= 0) {
             mp[pos] = q;
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
           bool of = false;
           for (int64_t e = g.rp[x]; e < g.rp[x + 1]; e++) {
             const int32_t y = g.col[e];
-            if (y >= u) break;
+            if (y >= ub) break;
             const int pb = find_key(s_k + kb, nb, y);
             if (pb < 0) continue;
             const int cy = A.colr[(int64_t)t * g.n + y];

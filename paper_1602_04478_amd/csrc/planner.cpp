@@ -243,7 +243,7 @@ static bool adjacent_in_cycle(const std::vector<int> &c, int a, int b) {
 }
 
 struct TreeScore {
-  int supported;     // 1 if every two-boundary block has adjacent boundary nodes
+  int no_pairs;      // 1 if every two-boundary block has adjacent boundary nodes (no pair-keyed table)
   int root_is_cycle; // prefer a cycle root (no table for it)
   int longest, sumbd, nann;
 };
@@ -255,15 +255,16 @@ static TreeScore score(const Tree &t) {
     s.sumbd += (int)B.boundary.size();
     for (int c : B.node_child) s.nann += c >= 0;
     for (int c : B.edge_child) s.nann += c >= 0;
-    if (B.boundary.size() == 2 && !adjacent_in_cycle(B.nodes, B.boundary[0], B.boundary[1])) s.supported = 0;
+    if (B.boundary.size() == 2 && !adjacent_in_cycle(B.nodes, B.boundary[0], B.boundary[1])) s.no_pairs = 0;
   }
   s.root_is_cycle = !t.blocks.empty() && t.blocks.back().kind == BK_ROOT_CYCLE;
   return s;
 }
 
 static bool better(const TreeScore &a, const TreeScore &b) {
-  // supported first; then the heuristic of Section 6; then a cycle root
-  if (a.supported != b.supported) return a.supported > b.supported;
+  // trees without pair-keyed tables first (those tables can be quadratic in
+  // the data graph); then the heuristic of Section 6; then a cycle root
+  if (a.no_pairs != b.no_pairs) return a.no_pairs > b.no_pairs;
   if (a.longest != b.longest) return a.longest < b.longest;
   if (a.sumbd != b.sumbd) return a.sumbd < b.sumbd;
   if (a.nann != b.nann) return a.nann < b.nann;
@@ -279,8 +280,13 @@ struct Search {
   bool have = false;
   Tree best;
   TreeScore best_score{};
+  int best_index = -1;
   int states = 0;
   bool found_any = false;
+  // every distinct tree, in the order found (kept up to kMaxTrees)
+  static constexpr size_t kMaxTrees = 4096;
+  std::vector<Tree> trees;
+  std::vector<TreeScore> scores;
 
   void finish(WQ &w, Tree &t) {
     // the last live node, if any, becomes a singleton root
@@ -303,10 +309,15 @@ struct Search {
     found_any = true;
     if (!seen_trees.insert(key).second) return;
     TreeScore s = score(tt);
+    if (trees.size() < kMaxTrees) {
+      trees.push_back(tt);
+      scores.push_back(s);
+    }
     if (!have || better(s, best_score)) {
       have = true;
       best = tt;
       best_score = s;
+      best_index = trees.size() <= kMaxTrees ? (int)trees.size() - 1 : -1;
     }
   }
 
@@ -520,7 +531,7 @@ static Program build_program(const Plan &plan, int bi) {
   };
   int nb = (int)B.boundary.size();
   int edge_i = -1, first_is_lo = 0;
-  if (nb == 2) {
+  if (nb == 2 && !B.pair_keyed) {
     int pf = posof(B.boundary[0]), ps = posof(B.boundary[1]);
     if (ps == (pf + 1) % L) {
       edge_i = pf;
@@ -530,7 +541,19 @@ static Program build_program(const Plan &plan, int bi) {
       first_is_lo = 0;
     }
   }
+  // path splitting: one h only -- the first boundary node (a_0 at the root);
+  // a pair-keyed block splits at its two boundary nodes
+  const int h_ps = nb == 0 ? 0 : posof(B.boundary[0]);
   for (int h = 0; h < L; h++) {
+    if (B.ps && h != h_ps) continue;
+    if (B.pair_keyed) {
+      const int d = posof(B.boundary[1]);
+      const int lx = ((d - h) % L + L) % L;
+      Chain x = pb.path(h, +1, lx, false, true);
+      Chain y = pb.path(h, -1, L - lx, true, false);
+      reqs.push_back({OP_MPAIR, x, y, 1});
+      continue;
+    }
     if (nb == 0 || (nb == 1 && posof(B.boundary[0]) == h)) {
       Chain pp = pb.path(h, +1, half, false, true);
       Chain pm = pb.path(h, -1, L - half, true, false);
@@ -559,15 +582,18 @@ static Program build_program(const Plan &plan, int bi) {
       }
     }
   }
-  // Symmetric merges (root, MU, MV): put the more frequent side second.
+  // Symmetric merges (root, MU, MV, pair): put the more frequent side second.
+  auto symmetric = [](int kind) {
+    return kind == OP_MROOT || kind == OP_MU || kind == OP_MV || kind == OP_MPAIR;
+  };
   std::map<Chain, int> freq;
   for (auto &r : reqs)
-    if (r.kind == OP_MROOT || r.kind == OP_MU || r.kind == OP_MV) {
+    if (symmetric(r.kind)) {
       freq[r.x]++;
       freq[r.y]++;
     }
   for (auto &r : reqs)
-    if (r.kind == OP_MROOT || r.kind == OP_MU || r.kind == OP_MV) {
+    if (symmetric(r.kind)) {
       int fx = freq[r.x], fy = freq[r.y];
       if (fx > fy || (fx == fy && r.y < r.x)) std::swap(r.x, r.y);
     }
@@ -648,7 +674,7 @@ static Program build_program(const Plan &plan, int bi) {
 
 }  // namespace
 
-Plan make_plan(int k, const std::vector<std::pair<int, int>> &edges) {
+Plan make_plan(int k, const std::vector<std::pair<int, int>> &edges, int mode, int tree) {
   if (k < 2 || k > 12) fail(CC_E_K_RANGE, "k must be in [2, 12]");
   WQ w;
   w.k = k;
@@ -679,19 +705,48 @@ Plan make_plan(int k, const std::vector<std::pair<int, int>> &edges) {
     for (int x = 0; x < k; x++)
       if (!seen[x]) fail(CC_E_QUERY_DISCONNECTED, "query is not connected");
   }
+  if (mode != PLAN_DB && mode != PLAN_PS) fail(CC_E_ARG, "unknown plan mode");
   Plan plan;
   plan.k = k;
+  plan.mode = mode;
   plan.edges = edges;
   plan.aut = count_aut(k, w.adj);
   Search S;
   S.rec(w, Tree());
   if (!S.have) fail(CC_E_QUERY_TW, "no decomposition into leaf edges and contractible cycles: treewidth > 2");
-  if (!S.best_score.supported)
-    fail(CC_E_UNSUPPORTED, "every decomposition has a block with two non-adjacent boundary nodes");
-  plan.blocks = S.best.blocks;
-  plan.longest_cycle = S.best_score.longest;
-  plan.sum_boundary = S.best_score.sumbd;
-  plan.num_annotations = S.best_score.nann;
+  plan.num_trees = (int)S.trees.size();
+  const Tree *pick = &S.best;
+  TreeScore sc = S.best_score;
+  plan.tree = S.best_index;
+  if (tree >= 0) {
+    if (tree >= (int)S.trees.size()) fail(CC_E_ARG, "no decomposition tree of that index");
+    pick = &S.trees[tree];
+    sc = S.scores[tree];
+    plan.tree = tree;
+  }
+  plan.blocks = pick->blocks;
+  plan.longest_cycle = sc.longest;
+  plan.sum_boundary = sc.sumbd;
+  plan.num_annotations = sc.nann;
+  // children come before parents, so a flag is final when a parent reads it
+  for (auto &B : plan.blocks) {
+    if (B.kind != BK_CYCLE && B.kind != BK_ROOT_CYCLE) continue;
+    if (B.boundary.size() == 2) {
+      if (!adjacent_in_cycle(B.nodes, B.boundary[0], B.boundary[1])) {
+        B.pair_keyed = true;
+      } else {
+        // adjacent boundary nodes joined by an edge that is itself a pair
+        // table's: the block's table is keyed by those pairs as well
+        const int L = (int)B.nodes.size();
+        for (int i = 0; i < L; i++) {
+          const int x = B.nodes[i], y = B.nodes[(i + 1) % L];
+          const bool bedge = (x == B.boundary[0] && y == B.boundary[1]) || (x == B.boundary[1] && y == B.boundary[0]);
+          if (bedge && B.edge_child[i] >= 0 && plan.blocks[B.edge_child[i]].pair_keyed) B.pair_keyed = true;
+        }
+      }
+    }
+    B.ps = mode == PLAN_PS || B.pair_keyed;
+  }
   plan.programs.assign(plan.blocks.size(), Program());
   for (size_t i = 0; i < plan.blocks.size(); i++)
     if (plan.blocks[i].kind == BK_CYCLE || plan.blocks[i].kind == BK_ROOT_CYCLE)

@@ -64,8 +64,37 @@ def test_planner_rejects():
         cc.Query(3, [(0, 1), (1, 1)])
     assert e.value.name == "CC_E_ARG"
     with pytest.raises(cc.CCError) as e:
-        cc.Query(*Q.k23())   # every tree needs a pair-keyed table
-    assert e.value.name == "CC_E_UNSUPPORTED"
+        cc.Query(3, [(0, 1), (1, 2)], tree=99)
+    assert e.value.name == "CC_E_ARG"
+
+
+def test_pair_keyed_plans():
+    """Queries every tree of which has a block with two non-adjacent boundary
+    nodes (K_{2,3}, the theta graph, the worked example of Section 4.1)
+    plan, with a pair-keyed block; queries that need none keep edge-keyed
+    tables only; path-splitting plans exist for every query."""
+    from paper_1602_04478_amd import cc
+    theta = (6, [(0, 1), (1, 2), (2, 3), (0, 4), (4, 3), (0, 5), (5, 3)])
+    for k, E in (Q.k23(), theta, Q.satellite()):
+        q = cc.Query(k, E)
+        ti = q.tree_info()
+        assert ti["pair_keyed_blocks"] >= 1 and 0 <= ti["tree"] < ti["num_trees"]
+        assert cc.Query(k, E, path_splitting=True).tree_info()["pair_keyed_blocks"] >= 1
+    for k, E in (Q.cycle_pendant(6), Q.domino_tail(), Q.cycle(5)):
+        assert cc.Query(k, E).tree_info()["pair_keyed_blocks"] == 0
+        assert cc.Query(k, E, path_splitting=True).info()["num_blocks"] == cc.Query(k, E).info()["num_blocks"]
+
+
+def test_every_tree_plans():
+    """Every tree index of the enumeration gives a plan; the heuristic's tree
+    is one of them."""
+    from paper_1602_04478_amd import cc
+    for k, E in (Q.domino_tail(), (8, Q.cycle(8)[1] + [(0, 4)]), Q.satellite()):
+        q = cc.Query(k, E)
+        nt = q.tree_info()["num_trees"]
+        assert nt >= 1
+        for t in range(nt):
+            assert cc.Query(k, E, tree=t).tree_info()["tree"] == t
 
 
 def test_planner_trees():

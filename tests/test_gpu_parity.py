@@ -145,3 +145,77 @@ def test_reverse_ties_same_total():
     a = cc.count(cc.Graph.from_csr(g), q, 7, 2)[2]
     b = cc.count(cc.Graph.from_csr(g, cc.CC_GRAPH_REVERSE_TIES), q, 7, 2)[2]
     assert a == b
+
+
+# queries every decomposition tree of which has a block whose two boundary
+# nodes are not adjacent (a table keyed by vertex pairs)
+PAIR_SHAPES = {
+    "K23": Q.k23(),
+    "theta": (6, [(0, 1), (1, 2), (2, 3), (0, 4), (4, 3), (0, 5), (5, 3)]),
+    "satellite": Q.satellite(),
+    "K23+pendant": (6, Q.k23()[1] + [(2, 5)]),
+}
+
+PAIR_MODES = {"auto": {}, "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"}, "light": {"CC_DENSE": "none"}}
+
+
+@pytest.mark.parametrize("mode", sorted(PAIR_MODES))
+@pytest.mark.parametrize("name", sorted(PAIR_SHAPES))
+def test_pair_keyed_tables(small_graphs, name, mode, monkeypatch):
+    """Pair-keyed blocks (split at their two boundary nodes, the table laid
+    out as a graph over the nonzero pairs) and their parents, against the
+    oracle's binary tables."""
+    for key, val in PAIR_MODES[mode].items():
+        monkeypatch.setenv(key, val)
+    k, E = PAIR_SHAPES[name]
+    q = cc.Query(k, E)
+    assert q.tree_info()["pair_keyed_blocks"] >= 1
+    for gi, g in enumerate(small_graphs):
+        print(f"[parity] pair-keyed {name} graph{gi} n={g.n} m={g.m} mode={mode}", flush=True)
+        dg = cc.Graph.from_csr(g)
+        col = _colours(g.n, k, 2, seed=300 + gi)
+        counts, ovf, exact = cc.count_colors(dg, q, col)
+        for t in range(2):
+            want = O.db(g, k, E, col[t])
+            assert not ovf[t] and exact[t] == want, (name, gi, t, exact[t], want)
+        # one colouring per call as well
+        c1, o1, e1 = cc.count_colors(dg, q, col[1:2])
+        assert e1[0] == exact[1]
+
+
+PS_MODES = {"auto": {}, "dense": {"CC_DENSE": "all"}, "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
+            "light": {"CC_DENSE": "none"}, "light+fallback": {"CC_DENSE": "none", "CC_LIGHT_SCRATCH": "6000"}}
+
+
+@pytest.mark.parametrize("mode", sorted(PS_MODES))
+@pytest.mark.parametrize("name", sorted(set(SHAPES) | set(PAIR_SHAPES)))
+def test_path_splitting_plans(small_graphs, name, mode, monkeypatch):
+    """The path-splitting baseline (every cycle split at its boundary nodes,
+    no degree-order filter, one split per cycle) gives the same counts."""
+    for key, val in PS_MODES[mode].items():
+        monkeypatch.setenv(key, val)
+    k, E = SHAPES.get(name) or PAIR_SHAPES[name]
+    q = cc.Query(k, E, path_splitting=True)
+    for gi, g in enumerate(small_graphs):
+        print(f"[parity] path splitting {name} graph{gi} n={g.n} mode={mode}", flush=True)
+        dg = cc.Graph.from_csr(g)
+        col = _colours(g.n, k, 2, seed=400 + gi)
+        counts, ovf, exact = cc.count_colors(dg, q, col)
+        for t in range(2):
+            want = O.db(g, k, E, col[t])
+            assert not ovf[t] and exact[t] == want, (name, gi, t, exact[t], want)
+
+
+def test_every_tree_same_count(small_graphs):
+    """Every decomposition tree of a query gives the same count (the choice
+    of tree is a cost knob only)."""
+    for name, (k, E) in (("domino+tail", Q.domino_tail()), ("C8+chord", (8, Q.cycle(8)[1] + [(0, 4)])),
+                         ("satellite", Q.satellite())):
+        nt = cc.Query(k, E).tree_info()["num_trees"]
+        g = small_graphs[1]
+        dg = cc.Graph.from_csr(g)
+        col = _colours(g.n, k, 1, seed=500)
+        want = O.db(g, k, E, col[0])
+        for t in range(min(nt, 12)):
+            print(f"[parity] {name} tree {t} of {nt}", flush=True)
+            assert cc.count_colors(dg, cc.Query(k, E, tree=t), col)[2][0] == want, (name, t)

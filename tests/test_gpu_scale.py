@@ -1,15 +1,21 @@
 """Parity at the benchmark's sizes and on the shapes of the larger
 configurations.
 
-Full size (Chung-Lu n = 1e6, 6-cycle + pendant, k = 7): the oracle computes
-the share of sampled root sources one by one (its non-root tables in full);
-the device's per-source shares must equal them, and sum to its total.
-Scaled configurations (same generators, smaller n so that the oracle
-finishes in seconds): 8-node domino + tail with 64 colourings in trial
-groups, and 20 generated treewidth-2 queries of 4-10 nodes, against the
-oracle trial by trial.  Overflow: a sum that leaves 64 bits
-is reported exactly in 128 bits and flagged; an intermediate that leaves 64
-bits is flagged."""
+Full size (Chung-Lu n = 1e6, 6-cycle + pendant, k = 7): the device's
+per-source shares (matches by their highest vertex) against the oracle's for
+hubs of the first dense group, low-degree sources and mid-degree sources; the
+shares sum to the device's total.  Scaled configurations (the same
+generators, smaller n): the C2 shape at n = 30000, whose automatic tier
+choice runs dense groups, the one-workgroup tier and its hand-backs in one
+solve; domino + tail with all 64 colourings; the 20 generated queries with
+all 16 colourings each.  Expected values that take the oracle minutes come
+from tests/golden/scale_counts.json, written by
+tests/golden/make_scale_golden.py (oracle only).  Overflow: a sum that leaves
+64 bits is reported exactly in 128 bits and flagged; a table entry that
+leaves 64 bits is flagged, also when the count itself is small."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -26,7 +32,16 @@ def cl1m():
     return graphs.workload_graph("cl1m")
 
 
+def _gold(name):
+    data = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "scale_counts.json")))
+    return data[name]
+
+
 def test_full_size_sampled_sources(cl1m):
+    """Per-source shares at n = 1e6 against the oracle's: hubs of the first
+    dense group (ranks 40-63 from the top of the degree order) and sixteen
+    low-degree sources, from stored oracle values (the hubs take the oracle
+    minutes each), plus mid-degree sources computed here."""
     g = cl1m
     k, E = Q.cycle_pendant(6)
     chi = O.colours(g.n, k, 102, 0)
@@ -34,14 +49,23 @@ def test_full_size_sampled_sources(cl1m):
     q = cc.Query(k, E)
     print("[scale] cl1m C6+pendant per-source run", flush=True)
     counts, ovf, exact, per = cc.count_colors(dg, q, chi, per_source=True)
+    st = cc.last_solve_stats()
     assert not ovf[0]
     per = per[0]
     assert sum(per) == exact[0]
+    # the first dense group holds the 64 highest sources
+    assert st["dense_sources"] >= 64 and st["group_sources"] == 64, st
     # the same total from the seeded path
     assert cc.count(dg, q, 102, 1)[2][0] == exact[0]
+    gold = _gold("c2_sources")
+    assert gold["seed"] == 102 and gold["trial"] == 0
     deg = g.degrees()
     order = np.lexsort((np.arange(g.n), deg))[::-1]  # highest (degree, id) first
-    # sources of degree ~500, ~270 and ~170 (the oracle needs minutes per hub)
+    for r, s, v in zip(gold["ranks"], gold["sources"], gold["shares"]):
+        assert int(order[r]) == s
+        assert per[s] == int(v), (r, s, int(deg[s]))
+    assert sum(1 for v in gold["shares"] if int(v) > 0) >= 20
+    # sources of degree ~500, ~270 and ~170
     sample = list(order[3000:3008]) + list(order[6000:6008]) + list(order[10000:10004])
     print(f"[scale] oracle on {len(sample)} sources", flush=True)
     tot, vals = O.db(g, k, E, chi, reverse_ties=False, sources=sample)
@@ -50,38 +74,70 @@ def test_full_size_sampled_sources(cl1m):
     assert any(v > 0 for v in vals)
 
 
+def test_c2_shape_whole_solve_all_tiers():
+    """The C2 shape (Chung-Lu, exponent 2.1, 6-cycle + pendant, k = 7)
+    scaled to n = 30000: whole counts against the oracle's, with the
+    library's own tier choice running dense groups, the one-workgroup tier
+    and hand-backs from it in one solve."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_scale_golden", os.path.join(os.path.dirname(__file__), "golden", "make_scale_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    g = mk.c2_scaled_graph()
+    gold = _gold("c2_scaled")
+    k, E = Q.cycle_pendant(6)
+    dg = cc.Graph.from_csr(g)
+    q = cc.Query(k, E)
+    want = [int(x) for x in gold["counts"]]
+    print(f"[scale] c2 shape n={g.n} m={g.m}: two colourings in one call", flush=True)
+    counts, ovf, exact, _ = cc.count(dg, q, gold["seed"], len(want))
+    assert [int(x) for x in exact] == want and not ovf.any()
+    for t, w in enumerate(want):
+        print(f"[scale] c2 shape: colouring {t} alone", flush=True)
+        c1, o1, e1, _ = cc.count(dg, q, gold["seed"] + t, 1)
+        assert e1[0] == w and not o1[0]
+        st = cc.last_solve_stats()
+        assert st["dense_sources"] > 0 and st["light_sources"] > 0 and st["handed_back"] > 0, st
+
+
 def test_domino_tail_64_trials():
+    """The C3 shape (domino + tail, k = 8, 64 colourings) at n = 5000: every
+    colouring of the batched call and of the plain call against the oracle."""
     g = graphs.chung_lu(5000, 20.0, 2.2, None, seed=3)
     k, E = Q.domino_tail()
     dg = cc.Graph.from_csr(g)
     q = cc.Query(k, E)
+    gold = _gold("c3_scaled")
+    want = [int(x) for x in gold["counts"]]
     print("[scale] chung-lu 5000 domino+tail 64 colourings, batched", flush=True)
-    counts, ovf, est = cc.count_batch(dg, [q], [103], [64])
-    for t in (0, 33, 63):
-        want = O.db(g, k, E, O.colours(g.n, k, 103, t))
-        assert int(counts[t]) == want and not ovf[t], t
-    # trial groups of the plain path give the same counts
-    plain = cc.count(dg, q, 103, 64)[0]
+    counts, ovf, est = cc.count_batch(dg, [q], [gold["seed"]], [64])
+    assert [int(c) for c in counts] == want and not ovf.any()
+    plain = cc.count(dg, q, gold["seed"], 64)[0]
     assert np.array_equal(plain, counts)
 
 
 def test_generated_queries():
+    """The C4 shape (20 generated treewidth-2 queries of 4-10 nodes, 16
+    colourings each, one batched call) at n = 1000: every colouring of every
+    query against the oracle."""
     g = graphs.chung_lu(1000, 8.0, 2.1, None, seed=4)
     dg = cc.Graph.from_csr(g)
+    gold = _gold("c4_scaled")["queries"]
     qs = Q.random_queries(204, 20, 4, 10)
-    objs, kept = [], []
-    for k, E, fam in qs:
+    objs = []
+    for (k, E, fam), gq in zip(qs, gold):
+        assert gq["k"] == k and [tuple(e) for e in gq["edges"]] == [tuple(map(int, e)) for e in E]
         objs.append(cc.Query(k, E))
-        kept.append((k, E, fam))
-    print(f"[scale] {len(kept)} generated queries, 2 colourings each", flush=True)
-    counts, ovf, est = cc.count_batch(dg, objs, [204 + i for i in range(len(objs))], [2] * len(objs))
-    for i, (k, E, fam) in enumerate(kept):
-        for t in (1,):  # the second colouring runs as a graph replay
-            want = O.db(g, k, E, O.colours(g.n, k, 204 + i, t))
+    print(f"[scale] {len(objs)} generated queries, 16 colourings each, batched", flush=True)
+    counts, ovf, est = cc.count_batch(dg, objs, [gq["seed"] for gq in gold], [16] * len(objs))
+    for i, gq in enumerate(gold):
+        for t in range(16):
+            want = int(gq["counts"][t])
             if want >= 2**64:
-                assert ovf[2 * i + t], (i, fam)
+                assert ovf[16 * i + t], (i, t)
             else:
-                assert int(counts[2 * i + t]) == want and not ovf[2 * i + t], (i, k, fam, t)
+                assert int(counts[16 * i + t]) == want and not ovf[16 * i + t], (i, gq["family"], t)
 
 
 def _star_forest(hubs, leaves):
@@ -115,3 +171,20 @@ def test_intermediate_overflow_flagged():
     assert want >= 2**64
     counts, ovf, exact = cc.count_colors(cc.Graph.from_csr(g), cc.Query(k, E), chi)
     assert ovf[0] and int(counts[0]) == 2**64 - 1
+
+
+@pytest.mark.parametrize("leaves", [500, 2000])
+def test_table_overflow_with_small_count(leaves):
+    """A star table entry that leaves 64 bits while the count itself is
+    small (2 * 11!): flagged, never wrapped; and with fewer leaves (every
+    entry below 2^64) the exact count.  Expected values from the oracle with
+    its 64-bit table width check."""
+    g, chi = graphs.hub_and_clique(leaves)
+    k, E = Q.star_triangle(8)
+    want, wide = O.db_flagged(g, k, E, chi)
+    assert want < 2**64
+    counts, ovf, exact = cc.count_colors(cc.Graph.from_csr(g), cc.Query(k, E), chi)
+    if wide:
+        assert ovf[0] and int(counts[0]) == 2**64 - 1 and exact[0] == 2**128 - 1
+    else:
+        assert not ovf[0] and exact[0] == want and int(counts[0]) == want

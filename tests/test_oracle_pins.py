@@ -230,3 +230,24 @@ def test_lemma_41_every_treewidth2_query_decomposes():
     for k, E in (Q.k4(), Q.k33()):
         with pytest.raises(ValueError):
             O.plan(k, E)
+
+
+@pytest.mark.parametrize("leaves", [500, 2000])
+def test_table_width_flag_closed_forms(leaves):
+    """The 64-bit width check (tables are 64-bit, overflow flagged): a star
+    of 8 leaves with a triangle through its centre (k = 11) on a hub of
+    `leaves` leaves (no triangle) beside K_12.  Closed forms: every colourful
+    match lies in the clique, where every injective map is a match, so the
+    count is 2 * 11! (colour 0 twice, every other colour once); the star
+    table at the hub holds 8! * (leaves / 10)^8 for each 8 of its 10 leaf
+    colours, the largest entry of any table, and the flag must say whether
+    that reaches 2^64."""
+    g, chi = graphs.hub_and_clique(leaves)
+    k, E = Q.star_triangle(8)
+    count, flag = O.db_flagged(g, k, E, chi)
+    assert count == 2 * math.factorial(11)
+    assert O.db(g, k, E, chi) == count
+    per_colour = np.bincount(chi[1:leaves + 1], minlength=k)[1:]
+    assert np.all(per_colour == leaves // 10)
+    biggest = math.factorial(8) * (leaves // 10) ** 8
+    assert flag == (biggest >= 2**64)
