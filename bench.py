@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -31,7 +32,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cl1m", help="cl1m (the benchmark), er1000, uneven, serve")
+    ap.add_argument("--workload", default="cl1m",
+                    help="cl1m (the benchmark), er1000, uneven, serve, ps (degree-based vs path splitting), "
+                         "trees (every decomposition tree timed), precision (colour-coding CV vs colourings)")
+    ap.add_argument("--ps-n", default="100000,300000",
+                    help="sizes of the power-law stand-ins of the DB-vs-PS comparison")
     ap.add_argument("--uneven-n", type=int, default=20_000)
     ap.add_argument("--uneven-trials", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -306,6 +311,165 @@ def run_serve(a):
     print(json.dumps(out))
 
 
+def _timed_count(dg, q, seed, trials=1):
+    t0 = time.perf_counter()
+    r = __import__("paper_1602_04478_amd.cc", fromlist=["cc"]).count(dg, q, seed, trials)
+    return time.perf_counter() - t0, r
+
+
+def run_ps(a):
+    """The paper's headline comparison (Section 8: DB against its path-
+    splitting baseline PS) on the same kernels: PS splits every cycle at its
+    boundary nodes (the root at a node and the one opposite) and lets paths
+    take any vertex; DB starts them at the highest vertex.  Power-law
+    stand-ins of the C2 and C3 shapes at the sizes given; one colouring per
+    solve after a warm-up; counts must agree."""
+    from cc_inputs import graphs, queries as Q
+    from paper_1602_04478_amd import cc
+    rows = []
+    for n in [int(x) for x in a.ps_n.split(",") if x]:
+        for shape, (k, E), gen in (("C2 shape: 6-cycle + pendant, exponent 2.1", Q.cycle_pendant(6),
+                                    lambda n: graphs.chung_lu(n, 16.0, 2.1, 1e4 * (n / 1e6) ** (1 / 1.1), seed=2)),
+                                   ("C3 shape: domino + tail, exponent 2.2", Q.domino_tail(),
+                                    lambda n: graphs.chung_lu(n, 20.0, 2.2, None, seed=3))):
+            g = gen(n)
+            dg = cc.Graph.from_csr(g)
+            qdb, qps = cc.Query(k, E), cc.Query(k, E, path_splitting=True)
+            cc.count(dg, qdb, 7, 1)  # warm-up
+            t_db, r_db = _timed_count(dg, qdb, 11)
+            t_db2, _ = _timed_count(dg, qdb, 12)
+            cc.count(dg, qps, 7, 1) if t_db < 5 else None
+            t_ps, r_ps = _timed_count(dg, qps, 11)
+            row = {"shape": shape, "n": g.n, "m": g.m, "max_degree": int(g.degrees().max()),
+                   "db_s": min(t_db, t_db2), "ps_s": t_ps, "improvement_ps_over_db": t_ps / min(t_db, t_db2),
+                   "counts_equal": r_db[2] == r_ps[2] and bool(r_db[1][0] == r_ps[1][0]), "count": int(r_db[2][0])}
+            rows.append(row)
+            print(f"[bench] ps {shape} n={g.n}: DB {row['db_s']:.3f} s, PS {t_ps:.3f} s", file=sys.stderr, flush=True)
+    f = [r["improvement_ps_over_db"] for r in rows]
+    out = {"metric": "DB-vs-PS improvement factor (t_PS / t_DB, same kernels, one colouring)",
+           "value": float(np.exp(np.mean(np.log(f)))), "unit": "x (geometric mean)", "n_gpus": 1, "steps": 1,
+           "warmup": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "degree-based vs path splitting on power-law stand-ins"},
+           "max": max(f), "all_counts_equal": all(r["counts_equal"] for r in rows), "rows": rows}
+    print(json.dumps(out))
+
+
+def run_trees(a):
+    """Every decomposition tree of a query timed (Section 8: the choice of
+    tree changes the time by up to an order of magnitude; the heuristic of
+    Section 6 picks a good one): per query, each tree's solve of one
+    colouring after a warm-up, the heuristic's tree, the fastest, and whether
+    the counts agree.  Power-law stand-in (Chung-Lu n = 1e5, mean 16,
+    exponent 2.1) and queries with several trees (the 20 generated ones that
+    have more than one, plus domino + tail, the chorded 8-cycle and the
+    worked example of Section 4.1)."""
+    from cc_inputs import graphs, queries as Q
+    from paper_1602_04478_amd import cc
+    g = graphs.chung_lu(100_000, 16.0, 2.1, None, seed=12)
+    dg = cc.Graph.from_csr(g)
+    qs = [("domino+tail", *Q.domino_tail()), ("C8+chord(0,4)", 8, Q.cycle(8)[1] + [(0, 4)]),
+          ("satellite", *Q.satellite())]
+    for i, (k, E, fam) in enumerate(Q.random_queries(204, 20, 4, 10)):
+        qs.append((f"generated {i} ({fam}, k={k})", k, E))
+    rows = []
+    for name, k, E in qs:
+        h = cc.Query(k, E)
+        ti = h.tree_info()
+        nt = min(ti["num_trees"], 12)
+        if nt < 2:
+            continue
+        times, counts, failed = [], [], []
+        print(f"[bench] trees {name}: timing {nt} trees", file=sys.stderr, flush=True)
+        for t in range(nt):
+            q = cc.Query(k, E, tree=t)
+            try:
+                cc.count(dg, q, 5, 1)
+                dt, r = _timed_count(dg, q, 6)
+            except cc.CCError as e:  # e.g. a pair-keyed table larger than the device memory
+                failed.append((t, e.name))
+                times.append(float("inf"))
+                continue
+            times.append(dt)
+            counts.append(r[2][0])
+        if len(failed) == nt:
+            rows.append({"query": name, "trees": ti["num_trees"], "timed": 0, "failed": failed})
+            continue
+        best = int(np.argmin(times))
+        heur = ti["tree"] if ti["tree"] < nt else None
+        # the batched call's own choice (tree tuned online on 32 of its
+        # colourings), where a colouring takes well under a second
+        tuned = None
+        if max(times) < 1.0:
+            try:
+                cc.count_batch(dg, [h], [77], [32])
+                tuned = cc.last_tune_report()["tree"]
+            except cc.CCError:
+                pass
+        fin = [x for x in times if x != float("inf")]
+        rows.append({"query": name, "trees": ti["num_trees"], "timed": nt,
+                     "seconds": [x if x != float("inf") else None for x in times], "failed": failed,
+                     "heuristic": heur, "fastest": best, "batched_tuned": tuned,
+                     "tuned_over_best": (times[tuned] / times[best]) if tuned is not None and tuned < nt else None,
+                     "spread_max_over_min": max(fin) / min(fin),
+                     "heuristic_over_best": (times[heur] / times[best]) if heur is not None else None,
+                     "counts_equal": len(set(counts)) == 1})
+        print(f"[bench] trees {name}: {nt} trees, spread {max(fin) / min(fin):.2f}x", file=sys.stderr,
+              flush=True)
+    ho = [r["heuristic_over_best"] for r in rows if r.get("heuristic_over_best") is not None]
+    out = {"metric": "decomposition trees: heuristic time / best time", "value": float(np.mean(ho)) if ho else None,
+           "unit": "x (mean)", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": f"every tree (up to 12) of queries with several trees, Chung-Lu n={g.n} m={g.m}"},
+           "heuristic_optimal_fraction": float(np.mean([h <= 1.05 for h in ho])) if ho else None,
+           "batched_tuned_over_best": float(np.mean([r["tuned_over_best"] for r in rows
+                                                     if r.get("tuned_over_best") is not None] or [float("nan")])),
+           "max_spread": max((r["spread_max_over_min"] for r in rows if "spread_max_over_min" in r), default=None),
+           "all_counts_equal": all(r.get("counts_equal", True) for r in rows), "rows": rows}
+    print(json.dumps(out))
+
+
+def run_precision(a):
+    """Colour-coding precision (Section 8): the coefficient of variation
+    (standard deviation / mean) of the estimate made from T colourings, for
+    T = 3 and T = 10, over disjoint groups of 60 colourings solved in one
+    batched call; per (graph, query) pair, and the fraction of pairs with
+    CV <= 0.1.  Power-law and Erdos-Renyi stand-ins, cycle and generated
+    queries."""
+    from cc_inputs import graphs, queries as Q
+    from paper_1602_04478_amd import cc
+    gl = [("Chung-Lu n=1e5 mean 16 exp 2.1", graphs.chung_lu(100_000, 16.0, 2.1, None, seed=21)),
+          ("Chung-Lu n=1e5 mean 20 exp 2.5", graphs.chung_lu(100_000, 20.0, 2.5, None, seed=22)),
+          ("near-regular Chung-Lu n=2e4 mean 10 exp 8", graphs.chung_lu(20_000, 10.0, 8.0, None, seed=23))]
+    ql = [("C5", *Q.cycle(5)), ("C6+pendant", *Q.cycle_pendant(6)), ("domino+tail", *Q.domino_tail())]
+    for i, (k, E, fam) in enumerate(Q.random_queries(606, 5, 4, 8)):
+        ql.append((f"generated {i} ({fam}, k={k})", k, E))
+    T = 60
+    rows = []
+    for gname, g in gl:
+        dg = cc.Graph.from_csr(g)
+        for qname, k, E in ql:
+            q = cc.Query(k, E)
+            counts, ovf, _ = cc.count_batch(dg, [q], [1000 + len(rows)], [T])
+            if ovf.any():
+                continue
+            scale = k ** k / math.factorial(k) / q.info()["aut"]
+            est = counts.astype(np.float64) * scale
+            row = {"graph": gname, "query": qname, "mean_estimate": float(est.mean())}
+            for tt in (3, 10):
+                grp = est[: (T // tt) * tt].reshape(-1, tt).mean(axis=1)
+                row[f"cv_{tt}"] = float(grp.std(ddof=1) / grp.mean()) if grp.mean() > 0 else None
+            rows.append(row)
+    ok = [r for r in rows if r["cv_3"] is not None]
+    out = {"metric": "colour-coding precision: pairs with CV <= 0.1", "value": float(np.mean([r["cv_3"] <= 0.1 for r in ok])),
+           "unit": "fraction of (graph, query) pairs at 3 colourings", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": f"{len(gl)} stand-in graphs x {len(ql)} queries, {T} colourings each, CV over "
+                                  "disjoint groups of 3 and of 10"},
+           "fraction_cv_le_0.1_at_10": float(np.mean([r["cv_10"] <= 0.1 for r in ok if r["cv_10"] is not None])),
+           "rows": rows}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -315,6 +479,12 @@ def main():
         return run_uneven(a)
     if a.workload == "serve":
         return run_serve(a)
+    if a.workload == "ps":
+        return run_ps(a)
+    if a.workload == "trees":
+        return run_trees(a)
+    if a.workload == "precision":
+        return run_precision(a)
     from cc_inputs import graphs
     from paper_1602_04478_amd import cc
     gname, qname, k, trials, seed0 = WORKLOADS[a.workload]
@@ -392,6 +562,28 @@ def main():
                           "speedup_vs_plain": dt_plain / dt,
                           "counts_match_plain": all(int(bc[t]) == int(pl[t][0][0]) and int(bo[t]) == int(pl[t][1][0])
                                                     for t in range(B))}
+    if a.batch_trials > 0 and a.workload == "cl1m":
+        # the tiny configuration (G(1000, 10/999), 5-cycle, k = 5), where a
+        # solve is a handful of short launches: 64 colourings as 64 plain
+        # calls and as one batched call (trial groups, graph replays)
+        from cc_inputs import queries as Q
+        g1 = graphs.workload_graph("er1000")
+        d1, q1 = cc.Graph.from_csr(g1), cc.Query(*Q.cycle(5))
+        cc.count(d1, q1, 101, 1)
+        cc.count_batch(d1, [q1], [101], [8])
+        t1 = time.perf_counter()
+        p1 = [cc.count(d1, q1, 101 + t, 1) for t in range(64)]
+        dt_p = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        b1 = cc.count_batch(d1, [q1], [101], [64])
+        dt_b = time.perf_counter() - t1
+        rep = cc.last_tune_report()
+        out["batched_tiny"] = {"workload": f"er1000: n={g1.n} m={g1.m}; query C5; k=5; 64 colourings",
+                               "value": 64 * g1.m / dt_b, "plain_value": 64 * g1.m / dt_p,
+                               "unit": "colourings*edges/s", "seconds": dt_b, "plain_seconds": dt_p,
+                               "speedup_vs_plain": dt_p / dt_b, "trial_group": rep["trial_group"],
+                               "graph_replays": rep["graph_replays"],
+                               "counts_match_plain": all(int(b1[0][t]) == int(p1[t][0][0]) for t in range(64))}
     if not a.no_cpu_baseline:
         checked, out["cpu_baseline"] = cpu_baseline(g, k, E, seed0, a.cpu_sample_seconds)
         # the same colouring on the device with per-source shares: the sampled

@@ -225,7 +225,9 @@ cc_status cc_count_static(cc_graph g, cc_query q, uint64_t seed, int32_t trials,
  * contract, so the counts equal cc_count's).  The colourings of a query are
  * solved in trial groups that form the batch dimension of every launch; the
  * launch sequence of a trial group is captured once in a hipGraph and
- * replayed for the next groups (use_graphs).
+ * replayed for the next groups (use_graphs).  With several queries, up to
+ * four run side by side, each on a stream of the library's with a quarter of
+ * the free device memory (the call first waits for `stream`).
  *   counts / overflow  host, concatenated per query in order (sum of trials[i]).
  *   estimates          host, double[nq] or NULL.
  *   tuning             NULL: the trial-group size is tuned online on the
@@ -239,10 +241,14 @@ cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint6
 
 /*
  * What the calling thread's last cc_count_batch chose for its last query
- * (online tuning when `tuning` was NULL): the dense cut (the model's, half and
- * double, one colouring per group) and then the trial-group size (not tried
- * when one colouring takes 0.25 s or more), the candidates timed and their
- * seconds per colouring, and the graph replays.
+ * (online tuning when `tuning` was NULL): first the decomposition tree, when
+ * the query has several and at least 32 colourings are asked for (up to four
+ * trees, the heuristic's first, each timed on colourings of the call, the
+ * fastest kept; Section 8 reports trees of one query differing by up to an
+ * order of magnitude), then the dense cut (the model's, half and double, one
+ * colouring per group) and the trial-group size (not tried when one
+ * colouring takes 0.25 s or more), the candidates timed and their seconds per
+ * colouring, and the graph replays.
  */
 typedef struct {
   int32_t trial_group;
@@ -252,6 +258,10 @@ typedef struct {
   uint64_t graph_replays;
   int32_t dense_sources;         /* chosen dense cut (sources run as dense groups) */
   int32_t tried_dense_sources[8];
+  int32_t tree;                  /* chosen decomposition tree (index as in cc_query_create_ex) */
+  int32_t trees_tried;           /* trees timed (0: the query's own tree only) */
+  int32_t tried_tree[8];
+  double tried_tree_seconds[8];  /* seconds per colouring of each tree timed */
 } cc_tune_report;
 cc_status cc_last_tune_report(cc_tune_report *out);
 

@@ -278,7 +278,9 @@ class TuneReport(ctypes.Structure):
     _fields_ = [("trial_group", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("tried_trial_group", ctypes.c_int32 * 8), ("tried_seconds_per_colouring", ctypes.c_double * 8),
                 ("graph_replays", ctypes.c_uint64), ("dense_sources", ctypes.c_int32),
-                ("tried_dense_sources", ctypes.c_int32 * 8)]
+                ("tried_dense_sources", ctypes.c_int32 * 8), ("tree", ctypes.c_int32),
+                ("trees_tried", ctypes.c_int32), ("tried_tree", ctypes.c_int32 * 8),
+                ("tried_tree_seconds", ctypes.c_double * 8)]
 
 
 def last_tune_report() -> dict:
@@ -286,7 +288,9 @@ def last_tune_report() -> dict:
     r = TuneReport()
     _check(lib().cc_last_tune_report(ctypes.byref(r)))
     n = min(r.candidates, 8)
+    nt = min(r.trees_tried, 8)
     return {"trial_group": r.trial_group, "dense_sources": r.dense_sources, "graph_replays": int(r.graph_replays),
+            "tree": r.tree, "trees": [(r.tried_tree[i], r.tried_tree_seconds[i]) for i in range(nt)],
             "tried": [(r.tried_trial_group[i], r.tried_dense_sources[i], r.tried_seconds_per_colouring[i])
                       for i in range(n)]}
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <atomic>
 #include <thread>
 
 #include "cc_internal.h"
@@ -253,16 +254,82 @@ cc_status cc_count_batch(cc_graph g, int32_t nq, const cc_query *qs, const uint6
   return guard([&] {
     if (!g || nq < 0 || (nq > 0 && (!qs || !seeds || !trials || !counts || !overflow)))
       cc::fail(CC_E_ARG, "bad argument");
-    size_t off = 0;
     cc::ExecOptions o = opts_from(tuning);
     for (int i = 0; i < nq; i++)
       if (!qs[i] || trials[i] < 1) cc::fail(CC_E_ARG, "bad query or trial count");
-    for (int i = 0; i < nq; i++) {
-      auto r = cc::run_batched(*g->g, qs[i]->plan, trials[i], seeds[i], tuning ? &o : nullptr, (hipStream_t)stream);
-      write_results(qs[i]->plan, r, trials[i], counts + off, overflow + off, nullptr,
-                    estimates ? estimates + i : nullptr);
-      off += trials[i];
+    std::vector<size_t> off(nq + 1, 0);
+    for (int i = 0; i < nq; i++) off[i + 1] = off[i] + (size_t)trials[i];
+    // Several queries run side by side: up to four workers, each with a
+    // stream of its own and a share of the device memory, take the queries
+    // in order (the small launches of one overlap the others').  The call
+    // first waits for `stream`, and returns when every query is done.
+    int workers = std::min(nq, 4);
+    if (const char *ev = getenv("CC_BATCH_STREAMS")) workers = std::max(1, std::min(workers, atoi(ev)));
+    if (workers <= 1) {
+      for (int i = 0; i < nq; i++) {
+        auto r = cc::run_batched(*g->g, qs[i]->plan, trials[i], seeds[i], tuning ? &o : nullptr, (hipStream_t)stream);
+        write_results(qs[i]->plan, r, trials[i], counts + off[i], overflow + off[i], nullptr,
+                      estimates ? estimates + i : nullptr);
+      }
+      return;
     }
+    HIP_CHECK(hipSetDevice(g->g->device));
+    if (stream) HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    size_t fr = 0, tot = 0;
+    HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    const uint64_t share = (uint64_t)(fr * 0.85) / (uint64_t)workers;
+    std::atomic<int> next{0};
+    std::mutex emu;
+    cc_status est = CC_OK;
+    std::string emsg;
+    cc::TuneReport last{};
+    int last_i = -1;
+    auto work = [&]() {
+      hipStream_t st = nullptr;
+      try {
+        HIP_CHECK(hipSetDevice(g->g->device));
+        HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        for (;;) {
+          const int i = next.fetch_add(1);
+          if (i >= nq) break;
+          {
+            std::lock_guard<std::mutex> lk(emu);
+            if (est != CC_OK) break;
+          }
+          cc::ExecOptions oi = o;
+          if (!oi.mem_budget) oi.mem_budget = share;
+          auto r = cc::run_batched(*g->g, qs[i]->plan, trials[i], seeds[i], tuning ? &oi : nullptr, st, share);
+          write_results(qs[i]->plan, r, trials[i], counts + off[i], overflow + off[i], nullptr,
+                        estimates ? estimates + i : nullptr);
+          std::lock_guard<std::mutex> lk(emu);
+          if (i > last_i) {
+            last_i = i;
+            last = cc::last_tune();
+          }
+        }
+      } catch (const cc::Error &e) {
+        std::lock_guard<std::mutex> lk(emu);
+        if (est == CC_OK) {
+          est = e.st;
+          emsg = e.msg;
+        }
+      } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> lk(emu);
+        if (est == CC_OK) {
+          est = CC_E_DEVICE;
+          emsg = e.what();
+        }
+      }
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+    };
+    std::vector<std::thread> pool;
+    for (int w = 0; w < workers; w++) pool.emplace_back(work);
+    for (auto &t : pool) t.join();
+    if (est != CC_OK) cc::fail(est, emsg);
+    cc::set_last_tune(last);
   });
 }
 
@@ -279,6 +346,12 @@ cc_status cc_last_tune_report(cc_tune_report *out) {
     out->graph_replays = r.replays;
     out->dense_sources = r.dense_sources;
     for (int i = 0; i < 8; i++) out->tried_dense_sources[i] = r.tried_dense[i];
+    out->tree = r.tree;
+    out->trees_tried = r.trees_tried;
+    for (int i = 0; i < 8; i++) {
+      out->tried_tree[i] = r.tried_tree[i];
+      out->tried_tree_seconds[i] = r.tried_tree_seconds[i];
+    }
   });
 }
 

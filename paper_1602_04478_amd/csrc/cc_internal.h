@@ -193,10 +193,16 @@ struct TuneReport {
   int dense_sources = 0;     // chosen
   double tried_sec_per_colouring[8] = {0};
   uint64_t replays = 0;    // graph replays by the chosen solver
+  int tree = -1;           // chosen decomposition tree
+  int trees_tried = 0;
+  int tried_tree[8] = {0};
+  double tried_tree_seconds[8] = {0};
 };
+// mem_budget: device bytes the tuned solvers may use (0: from the free memory)
 CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t seed, const ExecOptions *tuning,
-                        hipStream_t stream);
+                        hipStream_t stream, uint64_t mem_budget = 0);
 TuneReport last_tune();  // of the calling thread's last run_batched
+void set_last_tune(const TuneReport &r);
 
 // How the calling thread's last solve (any counting call) split its sources
 // over the tiers, for the root block (the last cycle block of the plan).

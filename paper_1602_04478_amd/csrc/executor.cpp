@@ -370,7 +370,8 @@ struct Profiler {
     HIP_CHECK(hipStreamSynchronize(st));
     std::vector<uint64_t> hl((size_t)3 * PROF_LANES * std::max(1, nctr)), h(3 * (size_t)std::max(1, nctr), 0);
     if (nctr)
-      HIP_CHECK(hipMemcpy(hl.data(), ctrmem.p, sizeof(uint64_t) * 3 * PROF_LANES * nctr, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpyAsync(hl.data(), ctrmem.p, sizeof(uint64_t) * 3 * PROF_LANES * nctr, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
     for (int r = 0; r < nctr; r++)
       for (int l = 0; l < PROF_LANES; l++)
         for (int i = 0; i < 3; i++) h[3 * r + i] += hl[((size_t)r * PROF_LANES + l) * 3 + i];
@@ -800,7 +801,7 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
   if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
   HIP_CHECK(hipSetDevice(g.device));
   if (!st_ && !opt.arena) {  // the null stream cannot be captured: work on a stream of our own
-    HIP_CHECK(hipStreamCreate(&own_st_));
+    HIP_CHECK(hipStreamCreateWithFlags(&own_st_, hipStreamNonBlocking));
     st_ = own_st_;
     st = st_;
   }
@@ -1462,7 +1463,8 @@ void Solver::finish_pairs(size_t bi, int Tg) {
   if (cnt > Q.cap)
     fail(CC_E_NOMEM, "pair-keyed table of " + std::to_string(cnt) + " entries; memory for " + std::to_string(Q.cap));
   std::vector<int32_t> keys(2 * cnt);
-  if (cnt) HIP_CHECK(hipMemcpy(keys.data(), Q.keys.p, sizeof(int32_t) * 2 * cnt, hipMemcpyDeviceToHost));
+  if (cnt) HIP_CHECK(hipMemcpyAsync(keys.data(), Q.keys.p, sizeof(int32_t) * 2 * cnt, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
   // entries sorted by (u, v), for the slot -> entry lookup
   std::vector<int64_t> ent(cnt);
   for (uint64_t i = 0; i < cnt; i++) ent[i] = (int64_t)i;
@@ -1536,7 +1538,8 @@ void Solver::run_light(Light &L, bool probe, int Tg, Profiler *prof) {
     HIP_CHECK(hipMemcpyAsync(hc, L.d_ctr.p, 8, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     std::vector<int32_t> f(hc[1]);
-    if (hc[1]) HIP_CHECK(hipMemcpy(f.data(), L.d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost));
+    if (hc[1]) HIP_CHECK(hipMemcpyAsync(f.data(), L.d_fail.p, 4 * (size_t)hc[1], hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
     std::sort(f.begin(), f.end(), std::greater<int32_t>());
     std::vector<int32_t> keep;
     {
@@ -1687,9 +1690,10 @@ thread_local TuneReport g_last_tune;
 }
 
 TuneReport last_tune() { return g_last_tune; }
+void set_last_tune(const TuneReport &r) { g_last_tune = r; }
 
 CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t seed, const ExecOptions *given,
-                        hipStream_t st) {
+                        hipStream_t st, uint64_t mem_budget) {
   if (trials < 1) fail(CC_E_ARG, "trials must be >= 1");
   CountResult res;
   res.exact.assign(trials, 0);
@@ -1710,9 +1714,17 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
     g_last_tune = rep;
     return res;
   }
+  std::vector<std::unique_ptr<Plan>> plans;  // other trees' plans (they outlive the solvers)
   std::unique_ptr<Solver> best;
   double best_per = 0;
   int best_T = 1, best_dense = -1;
+  // 0. the decomposition tree (Section 8: trees of one query can differ
+  // several-fold in time): when the query has more than one and there are
+  // colourings to spare, up to four trees -- the heuristic's first -- each
+  // solve colourings like the candidates below, and the fastest is kept.
+  // Every tree gives the same counts, so those colourings are results.
+  const Plan *pl = &p;
+  rep.tree = p.tree;
   // one candidate: a solver for (trial group, dense cut), a first group that
   // learns the hand-backs, a timed replayed group; false when too few trials
   // are left to time it
@@ -1721,7 +1733,8 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
     o.use_graphs = 1;
     o.trial_group = cand_T;
     o.dense_sources = dense;
-    auto S = std::make_unique<Solver>(g, p, std::min(cand_T, trials), o, st);
+    o.mem_budget = mem_budget;
+    auto S = std::make_unique<Solver>(g, *pl, std::min(cand_T, trials), o, st);
     const int T = S->T();
     S->run_group_of_trials(t0, std::min(T, trials - t0), cs, res, nullptr);
     t0 += std::min(T, trials - t0);
@@ -1746,6 +1759,39 @@ CountResult run_batched(const DevGraph &g, const Plan &p, int trials, uint64_t s
     }
     return true;
   };
+  if (p.num_trees > 1 && p.tree >= 0 && trials >= 32) {
+    std::vector<int> cands{p.tree};
+    for (int t = 0; t < p.num_trees && cands.size() < 4; t++)
+      if (t != p.tree) cands.push_back(t);
+    double tbest = 0;
+    const Plan *pbest = &p;
+    for (size_t ci = 0; ci < cands.size() && t0 + 2 <= trials; ci++) {
+      const Plan *cand = &p;
+      if (ci > 0) {
+        plans.push_back(std::make_unique<Plan>(make_plan(p.k, p.edges, p.mode, cands[ci])));
+        cand = plans.back().get();
+      }
+      pl = cand;
+      best.reset();
+      best_per = 0;
+      const int before = rep.candidates;
+      if (!trial(1, -1)) break;
+      const double per = rep.tried_sec_per_colouring[std::min(before, 7)];
+      if (ci < 8) {
+        rep.tried_tree[ci] = cands[ci];
+        rep.tried_tree_seconds[ci] = per;
+      }
+      rep.trees_tried = (int)ci + 1;
+      if (ci == 0 || per < tbest) {
+        tbest = per;
+        pbest = cand;
+      }
+    }
+    pl = pbest;
+    rep.tree = pl->tree;
+    best.reset();  // the dense cut and trial group are tuned on the chosen tree
+    best_per = 0;
+  }
   // 1. the dense cut, one colouring per group: the cost model's, half, double
   if (t0 < trials && trial(1, -1)) {
     const int d0 = best_dense;

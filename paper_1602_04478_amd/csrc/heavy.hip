@@ -1876,7 +1876,7 @@ bool ejmaps_prepare(int k) {
         }
     uint32_t *d = (uint32_t *)table_pool_alloc(bytes);
     if (!d) return false;
-    if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+    if (!upload_sync(d, h.data(), bytes)) return false;
     M.d[ra] = d;
     M.words[ra] = (int)(bytes / 4);
     M.cp[ra] = cp;
@@ -1947,7 +1947,7 @@ static bool njmaps_build(int dev, int k) {  // ejm_mu held
       }
       uint32_t *d = (uint32_t *)table_pool_alloc(h.size());
       if (!d) return false;
-      if (hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) return false;
+      if (!upload_sync(d, h.data(), h.size())) return false;
       M.d[ro][rA] = d;
       M.words[ro][rA] = (int)(h.size() / 4);
       M.ns[ro][rA] = ns;

@@ -117,6 +117,8 @@ const uint16_t *lut_device(int device);
 // Bytes of the constant-table pool (static device memory) on the current
 // device, 256-byte aligned; null when the pool is full or the lookup fails.
 void *table_pool_alloc(size_t bytes);
+// copy host -> device on a private non-blocking stream and wait (one-time table uploads)
+bool upload_sync(void *d, const void *h, size_t bytes);
 // trials x slots of one frontier row: EdgeJoin keeps two accumulator words per
 // slot in LDS, within 64 KiB per workgroup with its rank tables
 inline int max_row_slots() { return 3584; }

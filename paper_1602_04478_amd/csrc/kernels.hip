@@ -175,6 +175,17 @@ inline int grid_for(int64_t entries, int P) {
 }  // namespace
 
 
+// A one-time host-to-device copy on a stream of its own (non-blocking: it
+// must not touch the legacy stream, which other threads' stream captures
+// forbid), waited for before returning.
+bool upload_sync(void *d, const void *h, size_t bytes) {
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+  bool ok = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+  (void)hipStreamDestroy(s);
+  return ok;
+}
+
 // colex rank / unrank tables (per device, built once, in the constant-table pool)
 const uint16_t *lut_device(int device) {
   static std::mutex mu;
@@ -207,7 +218,7 @@ const uint16_t *lut_device(int device) {
   }
   uint16_t *d = (uint16_t *)table_pool_alloc(sizeof(uint16_t) * LUT_SIZE);
   if (!d) return nullptr;
-  if (hipMemcpy(d, h.data(), sizeof(uint16_t) * LUT_SIZE, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  if (!upload_sync(d, h.data(), sizeof(uint16_t) * LUT_SIZE)) return nullptr;
   tabs[device] = d;
   return d;
 }

@@ -99,3 +99,23 @@ def test_estimate_matches_formula(g_small):
     import math
     want = sum(int(c) for c in counts) * k ** k / (8 * math.factorial(k) * aut)
     assert est[0] == pytest.approx(want, rel=1e-12)
+
+
+def test_batched_tunes_the_tree():
+    """With 32 or more colourings and several decomposition trees, the
+    batched call times up to four trees on colourings of the call and keeps
+    the fastest; the counts equal the plain per-colouring counts."""
+    from cc_inputs import queries as Q
+    from oracle import oracle as O
+    g = graphs.chung_lu(2000, 8.0, 2.1, None, seed=61)
+    dg = cc.Graph.from_csr(g)
+    k, E = Q.domino_tail()
+    q = cc.Query(k, E)
+    assert q.tree_info()["num_trees"] >= 2
+    counts, ovf, est = cc.count_batch(dg, [q], [71], [32])
+    rep = cc.last_tune_report()
+    assert len(rep["trees"]) >= 2 and rep["tree"] in [t for t, _ in rep["trees"]]
+    plain = cc.count(dg, q, 71, 32)[0]
+    assert np.array_equal(plain, counts) and not ovf.any()
+    for t in (0, 31):
+        assert int(counts[t]) == O.db(g, k, E, O.colours(g.n, k, 71, t))
