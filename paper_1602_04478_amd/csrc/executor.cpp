@@ -172,7 +172,7 @@ struct RegBuf {
   DevMem val, mask;
 };
 struct LevelBuf {
-  DevMem mb, list, cnt, bcnt;
+  DevMem mb, list, cnt, bcnt, vlist;
 };
 
 int table_C(const Plan &p, int blk) {
@@ -762,6 +762,7 @@ class Solver {
     L.list = levels_[d].list.as<int64_t>();
     L.cnt = levels_[d].cnt.as<uint32_t>();
     L.bcnt = levels_[d].bcnt.as<uint32_t>();
+    L.vlist = levels_[d].vlist.as<int32_t>();
     return L;
   }
 
@@ -938,8 +939,9 @@ Solver::Solver(const DevGraph &g, const Plan &p, int trials, const ExecOptions &
     L.mb.alloc(2 * sizeof(uint64_t) * (size_t)nlim_max_);
     launch_fill_u64(L.mb.as<uint64_t>(), 2 * nlim_max_, st);
     L.list.alloc(sizeof(int64_t) * nf_max);
-    L.cnt.alloc(sizeof(uint32_t));
-    L.bcnt.alloc(sizeof(uint32_t) * (size_t)level_chunks(nlim_max_));
+    L.cnt.alloc(2 * sizeof(uint32_t));
+    L.bcnt.alloc(2 * sizeof(uint32_t) * (size_t)level_chunks(nlim_max_));
+    L.vlist.alloc(sizeof(int32_t) * (size_t)nlim_max_);
   }
   // pair-keyed blocks: the staging register of their merges and the entry
   // list, whose capacity is what the memory left holds (with room for the

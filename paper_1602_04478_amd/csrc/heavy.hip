@@ -125,11 +125,11 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
   __syncthreads();
   const int teams = BLK / TEAM, team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
   uint64_t prd = 0, pwr = 0;  // profiling: bytes read, written
-  for (int64_t v = (int64_t)blockIdx.x * teams + team; v < grp.n_lim; v += (int64_t)gridDim.x * teams) {
+  const int64_t nvin = Lin.cnt[1];  // the input level's marked vertices (listed in order)
+  for (int64_t i = (int64_t)blockIdx.x * teams + team; i < nvin; i += (int64_t)gridDim.x * teams) {
+    const int64_t v = Lin.vlist[i];
     const uint64_t m = Lin.mb[2 * v];
-    prd += lane == 0 ? 8 : 0;
-    if (!m) continue;
-    prd += lane == 0 ? 16 : 0;
+    prd += lane == 0 ? 28 : 0;
     int umin = 0x7fffffff, umax = 0;
     for (uint64_t r = m; r; r &= r - 1) {
       const int u = s_u[__builtin_ctzll(r)];
@@ -180,61 +180,82 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t *s, uint32_t
   return base + inc - x;
 }
 
-// marks per chunk (thread t reads vertices lo + i * BLK + t: coalesced)
+// marks and marked vertices per chunk (thread t reads vertices lo + i * BLK + t:
+// coalesced); bcnt[chunk] and bcnt[chunks + chunk]
 __global__ void k_cmp_count(const uint64_t *mb, int64_t nv, uint32_t *bcnt, uint64_t *prof) {
-  __shared__ uint32_t s[BLK];
+  __shared__ uint32_t s[BLK], sv[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH;
-  uint32_t c = 0;
+  uint32_t c = 0, cv = 0;
   for (int i = 0; i < CPER; i++) {
     const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
-    if (v < nv) c += __popcll(mb[2 * v]);
+    if (v < nv) {
+      const uint64_t m = mb[2 * v];
+      c += __popcll(m);
+      cv += m != 0;
+    }
   }
   s[threadIdx.x] = c;
+  sv[threadIdx.x] = cv;
   __syncthreads();
   for (int o = BLK / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    if (threadIdx.x < o) {
+      s[threadIdx.x] += s[threadIdx.x + o];
+      sv[threadIdx.x] += sv[threadIdx.x + o];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) bcnt[blockIdx.x] = s[0];
+  if (threadIdx.x == 0) {
+    bcnt[blockIdx.x] = s[0];
+    bcnt[gridDim.x + blockIdx.x] = sv[0];
+  }
   prof_flush(prof, threadIdx.x == 0 ? 8 * (uint64_t)max((int64_t)0, min((int64_t)CH, nv - lo)) : 0, 0, 0);
 }
 
-// exclusive scan of the chunk counts (one workgroup); total into *cnt
+// exclusive scans of the chunk counts (one workgroup): entries into bcnt[0..nb)
+// and cnt[0], marked vertices into bcnt[nb..2nb) and cnt[1]
 __global__ void k_cmp_scan(uint32_t *bcnt, int nb, uint32_t *cnt) {
   __shared__ uint32_t s[BLK];
   const int per = (nb + BLK - 1) / BLK;
   const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
-  uint32_t sum = 0;
-  for (int i = lo; i < hi; i++) sum += bcnt[i];
-  uint32_t tot;
-  uint32_t run = block_scan(sum, s, tot);
-  for (int i = lo; i < hi; i++) {
-    const uint32_t x = bcnt[i];
-    bcnt[i] = run;
-    run += x;
+  for (int part = 0; part < 2; part++) {
+    uint32_t *b = bcnt + part * nb;
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; i++) sum += b[i];
+    uint32_t tot;
+    uint32_t run = block_scan(sum, s, tot);
+    for (int i = lo; i < hi; i++) {
+      const uint32_t x = b[i];
+      b[i] = run;
+      run += x;
+    }
+    if (threadIdx.x == 0) cnt[part] = tot;
   }
-  if (threadIdx.x == 0) *cnt = tot;
 }
 
-// number the marks: base[v] and the entry list, in (v, b) order
-__global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64_t *list, uint64_t *prof) {
+// number the marks: base[v] and the entry list, in (v, b) order, and the list
+// of marked vertices in order
+__global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64_t *list, int32_t *vlist,
+                           uint64_t *prof) {
   __shared__ uint32_t s[BLK];
   const int64_t lo = (int64_t)blockIdx.x * CH;
-  uint32_t run = boff[blockIdx.x];
+  uint32_t run = boff[blockIdx.x], vrun = boff[gridDim.x + blockIdx.x];
   uint64_t prd = 0, pwr = 0;
   for (int i = 0; i < CPER; i++) {
     const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
     const uint64_t mm = v < nv ? mb[2 * v] : 0;
-    uint32_t tot;
+    uint32_t tot, vtot;
     const uint32_t id0 = run + block_scan((uint32_t)__popcll(mm), s, tot);
+    const uint32_t vid = vrun + block_scan(mm != 0 ? 1u : 0u, s, vtot);
     if (v < nv) {
       mb[2 * v + 1] = id0;
       uint32_t id = id0;
       for (uint64_t r = mm; r; r &= r - 1) list[id++] = v * 64 + __builtin_ctzll(r);
+      if (mm) vlist[vid] = (int32_t)v;
       prd += 8;
-      pwr += 8 + 8 * (uint64_t)__popcll(mm);
+      pwr += 8 + 8 * (uint64_t)__popcll(mm) + (mm ? 4 : 0);
     }
     run += tot;
+    vrun += vtot;
   }
   prof_flush(prof, prd, pwr, 0);
 }
@@ -612,7 +633,8 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
   const bool hsplit = !EPI && grp.dense && grp.nh > 0;
   const uint32_t nh = hsplit ? (uint32_t)grp.nh : 0u;
   const uint32_t nlight = (uint32_t)(hsplit ? min(grp.n_lim, grp.split_lo) : grp.n_lim);
-  const uint32_t nitems = nh + nlight, wstride = gridDim.x * WPB * NG;
+  // sparse groups: only the vertices the output level marks (listed in order)
+  const uint32_t nitems = grp.dense ? nh + nlight : Lout.cnt[1], wstride = gridDim.x * WPB * NG;
   for (uint32_t wl = (blockIdx.x * WPB + tid / WAVE) * NG + lane / SW; wl < nitems; wl += wstride) {
     int w;
     int64_t r0, r1;  // the item's neighbour range
@@ -626,7 +648,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
       split = true;
       first_chunk = off == 0;
     } else {
-      w = hsplit ? (int)(nlight - 1u - (wl - nh)) : (int)wl;
+      w = !grp.dense ? Lout.vlist[wl] : hsplit ? (int)(nlight - 1u - (wl - nh)) : (int)wl;
       // w's edge range is loaded with its marks, not after them (one step
       // less on the chain of dependent loads)
       r0 = g.rp[w];
@@ -1778,7 +1800,7 @@ static void compact(const GroupDev &grp, LevelDev L, hipStream_t st) {
   const int nb = (int)((nv + CH - 1) / CH);
   hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, grp.prof);
   hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(BLK), 0, st, L.bcnt, nb, L.cnt);
-  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, L.list, grp.prof);
+  hipLaunchKernelGGL(k_cmp_emit, dim3(nb), dim3(BLK), 0, st, L.mb, nv, L.bcnt, L.list, L.vlist, grp.prof);
 }
 
 int64_t level_chunks(int64_t n_lim) { return (n_lim + CH - 1) / CH; }

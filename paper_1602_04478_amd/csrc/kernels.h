@@ -30,8 +30,9 @@ struct LevelDev {
   uint64_t *mb;     // [n_lim][2]: marks (bit b: (v, b) is an entry), then the index of v's first
                     // entry (entries numbered in (v, b) order) -- one 16-byte load per vertex
   int64_t *list;    // [entries] v * 64 + b
-  uint32_t *cnt;    // number of entries
-  uint32_t *bcnt;   // [chunks] compaction scratch
+  uint32_t *cnt;    // [0] number of entries, [1] number of marked vertices
+  uint32_t *bcnt;   // [2][chunks] compaction scratch: entries, then marked vertices, per chunk
+  int32_t *vlist;   // the marked vertices, ascending (cnt[1] of them)
 };
 
 // A frontier register: one row of T * C slots per entry of its level.
