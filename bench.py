@@ -73,7 +73,7 @@ KERNEL_OF = {  # profiled op name -> the HIP kernel that runs it
     "edgejoin": "k_ejv", "nodejoin": "k_nj", "axpy": "k_axpyn", "merge_root": "k_mroot", "init": "k_init",
     "merge_u": "k_munary", "merge_v": "k_munary", "merge_edge": "k_medge", "merge_edge_t": "k_medge_t",
     "level_build_sparse": "level build", "light": "k_light", "light_large": "k_light", "leaf": "k_leaf",
-    "root_single": "k_root_single",
+    "root_single": "k_root_single", "merge_root_terms": "k_mroot_terms", "merge_pair": "k_mpair",
 }
 
 

@@ -357,6 +357,10 @@ struct Profiler {
     recs.push_back(r);
     return c;
   }
+  // the current record's operation name (a launch that turned out to be another kind)
+  void rename(const std::string &nm) {
+    if (on && !recs.empty()) recs.back().name = nm;
+  }
   // algorithmic bytes of the current record computed on the host
   void add_fixed(double bytes) {
     if (on && !recs.empty()) recs.back().fixed += bytes;
@@ -1323,6 +1327,23 @@ void Solver::run_group(size_t bi, const Program &P, const Grp &G, int Tg, uint64
             sj++;
           }
           if (ta.size() > 1 || any_nj) {
+            // a chain read only by the root merge right after it is summed
+            // inside that merge's pass (linearity), never stored
+            if (sj < steps.size() && !steps[sj].fused) {
+              const Op &mr = P.ops[steps[sj].op];
+              int reads = 0;
+              for (auto &o : P.ops) reads += (o.a == op.dst) + (o.b == op.dst);
+              if (mr.kind == OP_MROOT && (mr.a == op.dst) != (mr.b == op.dst) && reads == 1) {
+                const int other = mr.a == op.dst ? mr.b : mr.a;
+                if (launch_mroot_terms(grp, g_.n, colr, lv(op.dst), lv(other), ta.data(), tn.data(), tw.data(),
+                                       (int)ta.size(), (int)slots_pair(k, P.reg_s[op.dst]), P.reg_s[op.dst],
+                                       regdev(other), mr.w, acc_, st)) {
+                  if (prof) prof->rename(std::string("merge_root_terms") + (G.dense ? "_dense" : "_sparse"));
+                  skip_until = sj + 1;
+                  break;
+                }
+              }
+            }
             launch_axpyn(grp, g_.n, colr, lv(op.a), ta.data(), tn.data(), tw.data(), (int)ta.size(), regdev(op.dst),
                          ovf, st);
             skip_until = sj;

@@ -1512,6 +1512,128 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
   prof_flush(grp.prof, prd, 0, 0);
 }
 
+// Root merge whose first operand is an AXPY chain read by nothing else:
+// count[t] += w * sum over rows of sum over R of (sum_q w_q term_q)[R] * b[K \ {chi u, chi v} \ R],
+// the chain's slots computed in the pass (a term is a register, or the
+// NodeJoin of a register with a node table through its split map) and never
+// stored.  By linearity this is the chain's AXPY followed by k_mroot, with the
+// same checked arithmetic, without writing and re-reading the chain's rows.
+// Slot-parallel like the AXPY chains: dense groups a wavefront per vertex over
+// its live (row, trial, slot) items, sparse groups one thread per item; each
+// thread keeps its products' 128-bit sum per trial.
+__device__ __forceinline__ uint64_t chain_slot(const AxpyTerms &tm, const uint32_t *s_jm, uint32_t on, bool below,
+                                               int64_t e, int64_t v, int t, int T, int c, int C, int cup, bool &of) {
+  uint64_t x = 0;
+  for (int q = 0; q < tm.n; q++) {
+    if (!((on >> q) & 1u)) continue;
+    uint64_t xq;
+    if (tm.nt[q].val) {
+      if (!below) continue;
+      const int ns = tm.jns[q];
+      const uint32_t *jm = jmap_at(tm, s_jm, q);
+      const uint8_t *xi = (const uint8_t *)jm + c * ns;
+      const uint16_t *yi = (const uint16_t *)(jm + ((C * ns + 3) >> 2)) + (cup * C + c) * ns;
+      xq = nj_slot_map(tm.a[q].val + (e * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi, yi, ns,
+                       of);
+    } else {
+      xq = tm.a[q].val[(e * T + t) * C + c];
+    }
+    if (xq) add_ck(x, mul_ck(tm.w[q], xq, of), of);
+  }
+  return x;
+}
+
+template <bool DENSE>
+__global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, const uint8_t *colr, LevelDev La,
+                                                     LevelDev Lb, AxpyTerms tm, int C, int sa, RegDev bb,
+                                                     uint64_t w, AccDev acc, const uint16_t *lut) {
+  __shared__ uint16_t s_yi[256];
+  __shared__ uint64_t s_acc[2 * 64];
+  __shared__ int32_t s_u[WAVE];
+  __shared__ uint8_t s_cu[WAVE * WAVE];
+  extern __shared__ uint32_t s_jm[];
+  load_sources(grp, colr, n, s_u, s_cu);
+  load_jmaps(tm, s_jm);
+  for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) s_acc[i] = 0;
+  const int T = grp.T, Cb = bb.C, k = grp.k, B = grp.B;
+  const uint32_t Kp = (1u << (k - 2)) - 1u;
+  for (int c = threadIdx.x; c < C; c += BLK) s_yi[c] = lut[LUT_RANK + (Kp & ~unrank(lut, sa - 2, c))];
+  __syncthreads();
+  const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
+  const int per = T * C;
+  uint64_t tlo = 0, thi = 0, prd = 0;  // this thread's sum (one trial)
+  uint32_t ofm = 0;
+  // one (row, trial, slot) item: its products into the thread's sum
+  auto item = [&](int64_t e, int64_t v, int b, int t, int c, uint32_t on) {
+    const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
+    if (cu == cv) return;
+    const int64_t eb = DENSE ? (((bb.mask[v] & bmask) >> b) & 1ull ? e : -1) : sparse_entry(Lb, v, b);
+    if (eb < 0) return;
+    bool of = false;
+    const uint64_t x = chain_slot(tm, s_jm, on, v < vbound(grp, s_u[b]), e, v, t, T, c, C, cu - (cv < cu), of);
+    prd += 8 * (uint64_t)(tm.n + 1);
+    if (of) ofm |= 1u << t;
+    if (!x) return;
+    const uint64_t y = bb.val[(eb * T + t) * Cb + s_yi[c]];
+    if (!y) return;
+    uint64_t pl = x * y, ph = __umul64hi(x, y);
+    if (w != 1) {
+      const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
+      const uint64_t h2 = ph * w + c2;
+      if (__umul64hi(ph, w) != 0 || h2 < c2) ofm |= 1u << t;
+      pl = l2;
+      ph = h2;
+    }
+    if (acc.per_src) atomic_add128(&acc.per_src[2 * ((int64_t)s_u[b] * T + t)], pl, ph);
+    if (T == 1) {
+      const uint64_t sl = tlo + pl;
+      thi += ph + (sl < pl ? 1u : 0u);
+      tlo = sl;
+    } else {
+      atomic_add128(&s_acc[2 * t], pl, ph);
+    }
+  };
+  if (DENSE) {
+    const int lane = threadIdx.x % 64;
+    const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
+    for (int64_t v = wave; v < grp.n_lim; v += nwave) {
+      uint64_t mt[4] = {0, 0, 0, 0}, m = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (q < tm.n) {
+          mt[q] = tm.a[q].mask[v] & bmask;
+          m |= mt[q];
+        }
+      if (!m) continue;
+      const int items = __popcll(m) * per;
+      for (int it = lane; it < items; it += 64) {
+        const int q0 = it / per, r = it - q0 * per, t = r / C, c = r - t * C;
+        const int b = nth_bit(m, q0);
+        uint32_t on = 0;
+        for (int q = 0; q < tm.n; q++) on |= (uint32_t)((mt[q] >> b) & 1ull) << q;
+        item(v * B + b, v, b, t, c, on);
+      }
+    }
+  } else {
+    const int64_t N = (int64_t)(*La.cnt) * per;
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
+      const int64_t e = i / per;
+      const int r = (int)(i - e * per), t = r / C, c = r - t * C;
+      int64_t v;
+      int b;
+      entry_vb(grp, La, e, v, b);
+      item(e, v, b, t, c, (1u << tm.n) - 1u);
+    }
+  }
+  for (int t = 0; t < T; t++)
+    if ((ofm >> t) & 1u) atomicOr(&acc.ovf[t], 1u);
+  if (tlo | thi) atomic_add128(&s_acc[0], tlo, thi);
+  __syncthreads();
+  for (int t = threadIdx.x; t < T; t += blockDim.x)
+    if (s_acc[2 * t] | s_acc[2 * t + 1]) atomic_add128(&acc.sum[2 * t], s_acc[2 * t], s_acc[2 * t + 1]);
+  prof_flush(grp.prof, prd, 0, 0);
+}
+
 // ------------------------------------------------------------------ merges into unary tables
 // at_u:  out[u_b][R'] += w * sum over splits of R' \ {chi v} of a[(v,b)] * b[(v,b)]
 // !at_u: out[v][R']   += w * (same products, R' \ {chi u_b})
@@ -2145,6 +2267,40 @@ void launch_fill_u64v(uint64_t *p, int64_t n, uint64_t x, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_v, dim3((unsigned)std::min<int64_t>((n + BLK - 1) / BLK, 8192)), dim3(BLK), 0, st, p, n,
                      x);
+}
+
+bool launch_mroot_terms(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb,
+                        const RegDev *a, const TabDev *nt, const uint64_t *wq, int nterms, int Ca, int sa, RegDev b,
+                        uint64_t w, AccDev acc, hipStream_t st) {
+  if (nterms < 1 || nterms > 4 || Ca > 256 || getenv_flag_off("CC_NJMAP") || getenv_flag_off("CC_FUSE_ROOT"))
+    return false;
+  AxpyTerms tm{};
+  tm.n = nterms;
+  size_t lds = 0;
+  for (int q = 0; q < nterms; q++) {
+    tm.a[q] = a[q];
+    tm.w[q] = wq[q];
+    tm.nt[q] = nt ? nt[q] : TabDev{nullptr, 0, 0};
+    tm.jm[q] = nullptr;
+    tm.jmw[q] = tm.jns[q] = 0;
+    if (tm.nt[q].val) {  // every NodeJoin term needs its split map
+      if (!njmap_find(grp.k, sa - 2, tm.nt[q].s - 1, Ca, a[q].C, tm.nt[q].C, &tm.jm[q], &tm.jmw[q], &tm.jns[q]))
+        return false;
+      lds += (size_t)tm.jmw[q] * 4;
+    } else if (a[q].C != Ca) {
+      return false;
+    }
+  }
+  if (lds > NJMAP_LDS_MAX) return false;
+  if (grp.dense) {
+    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
+    hipLaunchKernelGGL(k_mroot_terms<true>, dim3(gr), dim3(BLK), lds, st, grp, n, colr, La, Lb, tm, Ca, sa, b, w, acc,
+                       cur_lut());
+  } else {
+    hipLaunchKernelGGL(k_mroot_terms<false>, dim3(fgrid(grp, (int64_t)grp.T * Ca)), dim3(BLK), lds, st, grp, n, colr,
+                       La, Lb, tm, Ca, sa, b, w, acc, cur_lut());
+  }
+  return true;
 }
 
 void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,

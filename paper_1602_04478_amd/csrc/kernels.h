@@ -164,6 +164,12 @@ void launch_axpyn(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev 
                   const TabDev *nt, const uint64_t *w, int nterms, RegDev dst, uint32_t *ovf, hipStream_t st);
 void launch_mroot(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a, RegDev b,
                   uint64_t w, AccDev acc, hipStream_t st);
+// root merge whose first operand is an AXPY chain (terms as launch_axpyn's;
+// the chain's signature size sa, slots Ca) computed in the pass; false (nothing
+// launched) when a NodeJoin term has no split map or the chain does not fit
+bool launch_mroot_terms(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb,
+                        const RegDev *a, const TabDev *nt, const uint64_t *wq, int nterms, int Ca, int sa, RegDev b,
+                        uint64_t w, AccDev acc, hipStream_t st);
 void launch_munary(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,
                    RegDev b, uint64_t w, int at_u, uint64_t *out, int s_out, int C_out, uint32_t *ovf, hipStream_t st);
 void launch_medge(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,

@@ -49,6 +49,9 @@ PATH_MODES = {
     # hub schedule with tiny chunks: every vertex of degree > 4 runs as chunks of 2 neighbours
     "dense-split": {"CC_DENSE": "all", "CC_SPLIT_CHUNK": "2"},
     "dense-split3": {"CC_DENSE": "all", "CC_SPLIT_CHUNK": "3"},
+    # root merges read their AXPY chain as stored rows (the chain not summed inside the merge)
+    "nofuseroot-dense": {"CC_DENSE": "all", "CC_FUSE_ROOT": "0"},
+    "nofuseroot-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_FUSE_ROOT": "0"},
 }
 
 
