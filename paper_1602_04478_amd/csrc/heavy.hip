@@ -1564,10 +1564,12 @@ __global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, co
   uint64_t tlo = 0, thi = 0, prd = 0;  // this thread's sum (one trial)
   uint32_t ofm = 0;
   // one (row, trial, slot) item: its products into the thread's sum
-  auto item = [&](int64_t e, int64_t v, int b, int t, int c, uint32_t on) {
-    const int cu = s_cu[t * WAVE + b], cv = colr[(int64_t)t * n + v];
+  // bmv: dense -- the other operand's activity word at v; cv1: v's colour when
+  // one trial (both loaded once per vertex)
+  auto item = [&](int64_t e, int64_t v, int b, int t, int c, uint32_t on, uint64_t bmv, int cv1) {
+    const int cu = s_cu[t * WAVE + b], cv = (DENSE && T == 1) ? cv1 : colr[(int64_t)t * n + v];
     if (cu == cv) return;
-    const int64_t eb = DENSE ? (((bb.mask[v] & bmask) >> b) & 1ull ? e : -1) : sparse_entry(Lb, v, b);
+    const int64_t eb = DENSE ? ((bmv >> b) & 1ull ? e : -1) : sparse_entry(Lb, v, b);
     if (eb < 0) return;
     bool of = false;
     const uint64_t x = chain_slot(tm, s_jm, on, v < vbound(grp, s_u[b]), e, v, t, T, c, C, cu - (cv < cu), of);
@@ -1604,14 +1606,17 @@ __global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, co
           mt[q] = tm.a[q].mask[v] & bmask;
           m |= mt[q];
         }
+      const uint64_t bmv = bb.mask[v] & bmask;
+      m &= bmv;  // rows without a partner row add nothing
       if (!m) continue;
+      const int cv1 = T == 1 ? colr[v] : 0;
       const int items = __popcll(m) * per;
       for (int it = lane; it < items; it += 64) {
         const int q0 = it / per, r = it - q0 * per, t = r / C, c = r - t * C;
         const int b = nth_bit(m, q0);
         uint32_t on = 0;
         for (int q = 0; q < tm.n; q++) on |= (uint32_t)((mt[q] >> b) & 1ull) << q;
-        item(v * B + b, v, b, t, c, on);
+        item(v * B + b, v, b, t, c, on, bmv, cv1);
       }
     }
   } else {
@@ -1622,7 +1627,7 @@ __global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, co
       int64_t v;
       int b;
       entry_vb(grp, La, e, v, b);
-      item(e, v, b, t, c, (1u << tm.n) - 1u);
+      item(e, v, b, t, c, (1u << tm.n) - 1u, 0, 0);
     }
   }
   for (int t = 0; t < T; t++)
