@@ -78,6 +78,8 @@ KERNEL_OF = {  # profiled op name -> the HIP kernel that runs it
 
 
 def kernel_of(op_name):
+    if "_op" in op_name:  # CC_PROFILE_BY_OP=1: records per program operation
+        op_name = op_name[:op_name.index("_op")]
     base = op_name.rsplit("_", 1)[0] if op_name.endswith(("_dense", "_sparse")) else op_name
     return KERNEL_OF.get(base, base)
 

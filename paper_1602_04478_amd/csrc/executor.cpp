@@ -1268,6 +1268,11 @@ void Solver::run_group(size_t bi, const Program &P, const Grp &G, int Tg, uint64
     }
     if (prof) {
       std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
+      static const bool by_op = [] {
+        const char *ev = getenv("CC_PROFILE_BY_OP");
+        return ev && *ev == '1';
+      }();
+      if (by_op) nm += "_op" + std::to_string(stp.op);  // one record per operation of the program
       if (op.kind == OP_EJ) {
         // algorithmic bytes: a 4-byte neighbour id per scanned pair, an
         // input row (plus the annotated edge's table row) per relaxation,
