@@ -55,6 +55,7 @@ WORKLOADS = {
     # name: (graph, query, k, trials, seed)
     "cl1m": ("cl1m", "C6+pendant", 7, 1, 102),
     "er1000": ("er1000", "C5", 5, 1, 101),
+    "cl2m": ("cl2m", "domino+tail", 8, 1, 103),
 }
 
 
@@ -84,11 +85,12 @@ def kernel_of(op_name):
     return KERNEL_OF.get(base, base)
 
 
-def traffic_record(kernel, launches):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def traffic_record(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_cl1m_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -98,7 +100,7 @@ def traffic_record(kernel, launches):
     return rec["hbm_bytes_per_launch"]
 
 
-def roofline(tstats, cstats):
+def roofline(tstats, cstats, workload):
     """The dominant kernel (largest summed time over the timed steps, timed
     with HIP events on the library's stream) against the HBM peak.
 
@@ -126,7 +128,7 @@ def roofline(tstats, cstats):
     name = max(per_kernel, key=lambda x: per_kernel[x][1])
     launches, secs, byts, ops = per_kernel[name]
     ach = byts / secs / 1e9 if secs > 0 else 0.0
-    traffic = traffic_record(name, launches)
+    traffic = traffic_record(name, workload)
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic, "kernel": name, "ops": sorted(ops), "launches": launches,
             "avg_launch_ms": 1000.0 * secs / max(1, launches), "alg_bytes_per_launch": byts / max(1, launches)}
@@ -542,7 +544,7 @@ def main():
         cc.profile_enable(0)
         cstats = cc.profile_take()
         assert (int(c2[0][0]), int(c2[1][0])) == results[0], "counting pass disagrees with the timed step"
-        out["roofline"], out["kernels"] = roofline(tstats, cstats)
+        out["roofline"], out["kernels"] = roofline(tstats, cstats, a.workload)
         # the rate of a plain streaming copy on this device: what an HBM-bound kernel can reach
         out["roofline"]["copy_probe_GBps"] = cc.probe_copy(1 << 30, 10)
     if a.batch_trials > 0:

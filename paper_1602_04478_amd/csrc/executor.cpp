@@ -325,7 +325,7 @@ struct Profiler {
   };
   std::vector<Rec> recs;
   std::vector<uint64_t *> ctrs;
-  static constexpr int kMaxCtr = 16384;
+  static constexpr int kMaxCtr = 65536;  // records with counters per solve (larger graphs have more groups)
   int nctr = 0;
   DevMem ctrmem;
   explicit Profiler(hipStream_t s, bool allowed = true) : st(s) {

@@ -1639,6 +1639,253 @@ __global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, co
   prof_flush(grp.prof, prd, 0, 0);
 }
 
+// Lanes of one wavefront see each other's LDS writes after this (the
+// wavefront's LDS operations have completed and are ordered before the reads).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same merge for one colouring, by chunks of rows: a wavefront takes R =
+// IPL * 64 / C rows at a time, each lane IPL of the chunk's (row, slot) items.
+// Every global load of a chunk is issued before any is used: each item's slot
+// of the plain terms and its partner slot, and the chunk's rows of the
+// NodeJoin terms' inputs and node-table rows, which go to the wavefront's LDS
+// stage (coalesced: a chunk's rows are adjacent in the register); then every
+// item's splits are computed from LDS.  A chunk costs one memory latency
+// instead of a chain of dependent gathers per slot.  NT: the number of terms.
+// Stage layout per wavefront (64-bit words): for each NodeJoin term q, R rows
+// of a[q] (a[q].C words each) and then the node-table rows (one row in dense
+// groups, where a chunk shares its vertex; R rows in sparse groups).
+template <bool DENSE, int NT, int IPL>
+__global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, const uint8_t *colr, LevelDev La,
+                                                    LevelDev Lb, AxpyTerms tm, int C, int sa, RegDev bb,
+                                                    uint64_t w, AccDev acc, const uint16_t *lut, int jm_words,
+                                                    int stage_words) {
+  __shared__ uint16_t s_yi[256];
+  __shared__ uint64_t s_acc[2];
+  __shared__ int32_t s_u[WAVE];
+  __shared__ uint8_t s_cu[WAVE];
+  extern __shared__ uint64_t s_dyn[];  // split maps, then the stages
+  uint32_t *s_jm = (uint32_t *)s_dyn;
+  for (int i = threadIdx.x; i < WAVE; i += blockDim.x) {
+    s_u[i] = i < grp.B ? grp.src[i] : 0;
+    s_cu[i] = i < grp.B ? colr[grp.src[i]] : 0;
+  }
+  load_jmaps(tm, s_jm);
+  if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
+  const int k = grp.k, B = grp.B, Cb = bb.C;
+  const uint32_t Kp = (1u << (k - 2)) - 1u;
+  for (int c = threadIdx.x; c < C; c += BLK) s_yi[c] = lut[LUT_RANK + (Kp & ~unrank(lut, sa - 2, c))];
+  __syncthreads();
+  const int lane = threadIdx.x % 64;
+  uint64_t *stg = s_dyn + (jm_words + 1) / 2 + (size_t)(threadIdx.x / 64) * stage_words;
+  const int R = IPL * 64 / C;  // rows per chunk
+  int jr[IPL], c[IPL];         // the lane's items: row of the chunk, slot
+#pragma unroll
+  for (int i = 0; i < IPL; i++) {
+    jr[i] = (lane + 64 * i) / C;
+    c[i] = lane + 64 * i - jr[i] * C;
+  }
+  // stage offsets of the NodeJoin terms (rows of a[q], then node-table rows)
+  int off_a[NT], off_n[NT];
+  {
+    int off = 0;
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      off_a[q] = off_n[q] = 0;
+      if (!tm.nt[q].val) continue;
+      off_a[q] = off;
+      off += R * tm.a[q].C;
+      off_n[q] = off;
+      off += (DENSE ? 1 : R) * tm.nt[q].C;
+    }
+  }
+  const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
+  const bool same_level = La.mb == Lb.mb;  // sparse: the partner row has the same entry
+  uint64_t tlo = 0, thi = 0, prd = 0;
+  bool of = false;
+  // an item once its loads have landed: xp[q] the plain terms' slots, y the
+  // partner slot (0: the item adds nothing)
+  auto finish = [&](int jri, int ci, int b, int64_t v, uint32_t on, const uint64_t *xp, uint64_t y, int cv) {
+    const int cu = s_cu[b];
+    if (cu == cv) return;
+    const bool below = v < vbound(grp, s_u[b]);
+    const int cup = cu - (cv < cu);
+    prd += 8 * (uint64_t)(NT + 1);
+    if (!y) return;
+    uint64_t x = 0;
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      if (!((on >> q) & 1u)) continue;
+      uint64_t xq = 0;
+      if (tm.nt[q].val) {
+        if (!below) continue;
+        const int ns = tm.jns[q];
+        const uint32_t *jm = jmap_at(tm, s_jm, q);
+        const uint8_t *xi = (const uint8_t *)jm + ci * ns;
+        const uint16_t *yi = (const uint16_t *)(jm + ((C * ns + 3) >> 2)) + (cup * C + ci) * ns;
+        const uint64_t *ar = stg + off_a[q] + jri * tm.a[q].C;
+        const uint64_t *nr = stg + off_n[q] + (DENSE ? 0 : jri * tm.nt[q].C);
+        for (int j = 0; j < ns; j++) {
+          const uint64_t z = nr[yi[j]];
+          if (!z) continue;
+          const uint64_t xa = ar[xi[j]];
+          if (xa) add_ck(xq, mul_ck(xa, z, of), of);
+        }
+      } else {
+        xq = xp[q];
+      }
+      if (xq) add_ck(x, mul_ck(tm.w[q], xq, of), of);
+    }
+    if (!x) return;
+    uint64_t pl = x * y, ph = __umul64hi(x, y);
+    if (w != 1) {
+      const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
+      const uint64_t h2 = ph * w + c2;
+      if (__umul64hi(ph, w) != 0 || h2 < c2) of = true;
+      pl = l2;
+      ph = h2;
+    }
+    if (acc.per_src) atomic_add128(&acc.per_src[2 * (int64_t)s_u[b]], pl, ph);
+    const uint64_t sl = tlo + pl;
+    thi += ph + (sl < pl ? 1u : 0u);
+    tlo = sl;
+  };
+  const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
+  if (DENSE) {
+    for (int64_t v = wave; v < grp.n_lim; v += nwave) {
+      uint64_t mt[NT], m = 0;
+#pragma unroll
+      for (int q = 0; q < NT; q++) {
+        mt[q] = tm.a[q].mask[v] & bmask;
+        m |= mt[q];
+      }
+      m &= bb.mask[v] & bmask;  // rows without a partner row add nothing
+      if (!m) continue;
+      const int cv = colr[v];
+      const int nrows = __popcll(m);
+      for (int j0 = 0; j0 < nrows; j0 += R) {
+        // issue: the items' plain-term and partner slots, then the stage
+        int bi[IPL];
+        uint32_t on[IPL];
+        uint64_t xp[IPL][NT], y[IPL];
+#pragma unroll
+        for (int i = 0; i < IPL; i++) {
+          const bool act = jr[i] < R && j0 + jr[i] < nrows;
+          bi[i] = act ? nth_bit(m, j0 + jr[i]) : -1;
+          on[i] = 0;
+          y[i] = 0;
+#pragma unroll
+          for (int q = 0; q < NT; q++) xp[i][q] = 0;
+          if (act && s_cu[bi[i]] != cv) {
+            const int64_t row = v * B + bi[i];
+#pragma unroll
+            for (int q = 0; q < NT; q++) {
+              const bool hq = (mt[q] >> bi[i]) & 1ull;
+              on[i] |= (uint32_t)hq << q;
+              if (!tm.nt[q].val && hq) xp[i][q] = tm.a[q].val[row * C + c[i]];
+            }
+            y[i] = bb.val[row * Cb + s_yi[c[i]]];
+          }
+        }
+        if (j0 == 0) {
+#pragma unroll
+          for (int q = 0; q < NT; q++)
+            if (tm.nt[q].val)
+              for (int i = lane; i < tm.nt[q].C; i += 64) stg[off_n[q] + i] = tm.nt[q].val[v * tm.nt[q].C + i];
+        }
+#pragma unroll
+        for (int q = 0; q < NT; q++) {
+          if (!tm.nt[q].val) continue;
+          const int Cq = tm.a[q].C;
+          for (int i = lane; i < R * Cq; i += 64) {
+            const int r = i / Cq;
+            if (j0 + r >= nrows) break;
+            const int br = nth_bit(m, j0 + r);
+            if ((mt[q] >> br) & 1ull) stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
+          }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < IPL; i++)
+          if (bi[i] >= 0) finish(jr[i], c[i], bi[i], v, on[i], xp[i], y[i], cv);
+        wave_lds_sync();  // the stage is read before the next chunk overwrites it
+      }
+    }
+  } else {
+    const int64_t N = *La.cnt, nch = (N + R - 1) / R;
+    for (int64_t ch = wave; ch < nch; ch += nwave) {
+      const int64_t e0 = ch * R;
+      const int lim = N - e0 < R ? (int)(N - e0) : R;  // entries of this chunk
+      int64_t v[IPL];
+      int bi[IPL], cv[IPL];
+      uint64_t xp[IPL][NT], y[IPL];
+#pragma unroll
+      for (int i = 0; i < IPL; i++) {
+        const int64_t e = e0 + jr[i];
+        v[i] = 0;
+        bi[i] = -1;
+        cv[i] = 0;
+        y[i] = 0;
+#pragma unroll
+        for (int q = 0; q < NT; q++) xp[i][q] = 0;
+        if (jr[i] < lim) {
+          const int64_t x = La.list[e];
+          v[i] = x >> 6;
+          bi[i] = (int)(x & 63);
+          cv[i] = colr[v[i]];
+          const int64_t eb = same_level ? e : sparse_entry(Lb, v[i], bi[i]);
+          if (eb >= 0 && s_cu[bi[i]] != cv[i]) {
+#pragma unroll
+            for (int q = 0; q < NT; q++)
+              if (!tm.nt[q].val) xp[i][q] = tm.a[q].val[e * C + c[i]];
+            y[i] = bb.val[eb * Cb + s_yi[c[i]]];
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NT; q++) {
+        if (!tm.nt[q].val) continue;
+        const int Cq = tm.a[q].C, Cn = tm.nt[q].C;
+        for (int i = lane; i < lim * Cq; i += 64) stg[off_a[q] + i] = tm.a[q].val[e0 * Cq + i];
+        for (int i = lane; i < lim * Cn; i += 64) {
+          const int r = i / Cn;
+          const int64_t vr = La.list[e0 + r] >> 6;
+          stg[off_n[q] + i] = tm.nt[q].val[vr * Cn + (i - r * Cn)];
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < IPL; i++)
+        if (bi[i] >= 0) finish(jr[i], c[i], bi[i], v[i], (1u << NT) - 1u, xp[i], y[i], cv[i]);
+      wave_lds_sync();
+    }
+  }
+  if (of) atomicOr(&acc.ovf[0], 1u);
+  if (tlo | thi) atomic_add128(&s_acc[0], tlo, thi);
+  __syncthreads();
+  if (threadIdx.x == 0 && (s_acc[0] | s_acc[1])) atomic_add128(&acc.sum[0], s_acc[0], s_acc[1]);
+  prof_flush(grp.prof, prd, 0, 0);
+}
+
+template <bool DENSE, int IPL>
+void launch_mroot_rows_nt(int nt, dim3 gr, size_t lds, hipStream_t st, const GroupDev &grp, int64_t n,
+                          const uint8_t *colr, LevelDev La, LevelDev Lb, const AxpyTerms &tm, int C, int sa, RegDev b,
+                          uint64_t w, AccDev acc, const uint16_t *lut, int jm_words, int words) {
+#define CC_MR(NTV)                                                                                                   \
+  hipLaunchKernelGGL((k_mroot_rows<DENSE, NTV, IPL>), gr, dim3(BLK), lds, st, grp, n, colr, La, Lb, tm, C, sa, b, w, \
+                     acc, lut, jm_words, words)
+  switch (nt) {
+    case 1: CC_MR(1); break;
+    case 2: CC_MR(2); break;
+    case 3: CC_MR(3); break;
+    default: CC_MR(4); break;
+  }
+#undef CC_MR
+}
+
 // ------------------------------------------------------------------ merges into unary tables
 // at_u:  out[u_b][R'] += w * sum over splits of R' \ {chi v} of a[(v,b)] * b[(v,b)]
 // !at_u: out[v][R']   += w * (same products, R' \ {chi u_b})
@@ -2297,6 +2544,38 @@ bool launch_mroot_terms(const GroupDev &grp, int64_t n, const uint8_t *colr, Lev
     }
   }
   if (lds > NJMAP_LDS_MAX) return false;
+  // one colouring: chunks of rows staged in LDS per wavefront (CC_MROOT_ROWS=0: per-slot gathers)
+  if (grp.T == 1 && Ca <= 64 && !getenv_flag_off("CC_MROOT_ROWS")) {
+    // items per lane: 1 (CC_MROOT_IPL=2: two, more loads in flight but fewer wavefronts per SIMD; slower)
+    static const int ipl = [] {
+      const char *ev = getenv("CC_MROOT_IPL");
+      return ev && *ev == '2' ? 2 : 1;
+    }();
+    const int R = ipl * 64 / Ca;
+    int words = 0;
+    for (int q = 0; q < nterms; q++)
+      if (tm.nt[q].val) words += R * tm.a[q].C + (grp.dense ? 1 : R) * tm.nt[q].C;
+    const int jm_words = (int)(lds / 4);
+    words = std::max(1, words);
+    const size_t lds2 = (size_t)(jm_words + 1) / 2 * 8 + (size_t)(BLK / 64) * words * 8;
+    if (words <= 2048 && lds2 <= 64 * 1024) {
+      const dim3 gr(grp.dense ? (unsigned)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536)) : 8192u);
+      const uint16_t *lut = cur_lut();
+      if (grp.dense && ipl == 2)
+        launch_mroot_rows_nt<true, 2>(nterms, gr, lds2, st, grp, n, colr, La, Lb, tm, Ca, sa, b, w, acc, lut, jm_words,
+                                      words);
+      else if (grp.dense)
+        launch_mroot_rows_nt<true, 1>(nterms, gr, lds2, st, grp, n, colr, La, Lb, tm, Ca, sa, b, w, acc, lut, jm_words,
+                                      words);
+      else if (ipl == 2)
+        launch_mroot_rows_nt<false, 2>(nterms, gr, lds2, st, grp, n, colr, La, Lb, tm, Ca, sa, b, w, acc, lut,
+                                       jm_words, words);
+      else
+        launch_mroot_rows_nt<false, 1>(nterms, gr, lds2, st, grp, n, colr, La, Lb, tm, Ca, sa, b, w, acc, lut,
+                                       jm_words, words);
+      return true;
+    }
+  }
   if (grp.dense) {
     const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));
     hipLaunchKernelGGL(k_mroot_terms<true>, dim3(gr), dim3(BLK), lds, st, grp, n, colr, La, Lb, tm, Ca, sa, b, w, acc,
