@@ -102,6 +102,14 @@ __device__ __forceinline__ void prof_flush(uint64_t *prof, uint64_t c0, uint64_t
   }
 }
 
+// Lanes of one wavefront see each other's LDS writes after this (the
+// wavefront's LDS operations have completed and are ordered before the reads).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ levels (sparse groups)
 // depth 1: the lower neighbours of each source
 __global__ void k_mark_init(GraphDev g, GroupDev grp, const int32_t *lowcnt, int max_low, LevelDev L) {
@@ -1433,6 +1441,195 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
   prof_flush(grp.prof, prd, pwr, 0);
 }
 
+// One colouring: the AXPY chain by chunks of rows, like the root merge below
+// (a wavefront takes R = 64 / C rows, lane = (row of the chunk, slot); the
+// plain terms' slots are loaded by their lanes, the NodeJoin terms' input rows
+// and node-table rows are staged in the wavefront's LDS; every load of a chunk
+// is issued before any is used).  Dense groups write the activity word of
+// dst and its live rows; sparse groups every entry.  NT: the number of terms.
+template <bool DENSE, int NT>
+__global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, const uint8_t *colr, LevelDev L,
+                                                    AxpyTerms tm, RegDev dst, uint32_t *ovf, int jm_words,
+                                                    int stage_words) {
+  __shared__ int32_t s_u[WAVE];
+  __shared__ uint8_t s_cu[WAVE];
+  extern __shared__ uint64_t s_dyn[];  // split maps, then the stages
+  uint32_t *s_jm = (uint32_t *)s_dyn;
+  for (int i = threadIdx.x; i < WAVE; i += blockDim.x) {
+    s_u[i] = i < grp.B ? grp.src[i] : 0;
+    s_cu[i] = i < grp.B ? colr[grp.src[i]] : 0;
+  }
+  load_jmaps(tm, s_jm);
+  __syncthreads();
+  const int B = grp.B, C = dst.C;
+  const int lane = threadIdx.x % 64;
+  uint64_t *stg = s_dyn + (jm_words + 1) / 2 + (size_t)(threadIdx.x / 64) * stage_words;
+  const int R = 64 / C;
+  const int jr = lane / C, c = lane - jr * C;  // this lane's row of the chunk and slot
+  int off_a[NT], off_n[NT];
+  {
+    int off = 0;
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      off_a[q] = off_n[q] = 0;
+      if (!tm.nt[q].val) continue;
+      off_a[q] = off;
+      off += R * tm.a[q].C;
+      off_n[q] = off;
+      off += (DENSE ? 1 : R) * tm.nt[q].C;
+    }
+  }
+  const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
+  uint64_t prd = 0, pwr = 0;
+  bool of = false;
+  // the lane's slot of the chain once its loads have landed
+  auto slot = [&](int b, int64_t v, uint32_t on, const uint64_t *xp, int cv) -> uint64_t {
+    const int cu = s_cu[b];
+    const bool njok = v < vbound(grp, s_u[b]) && cu != cv;
+    const int cup = cu - (cv < cu);
+    uint64_t y = 0;
+#pragma unroll
+    for (int q = 0; q < NT; q++) {
+      if (!((on >> q) & 1u)) continue;
+      uint64_t xq = 0;
+      if (tm.nt[q].val) {
+        if (!njok) continue;
+        if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
+        const int ns = tm.jns[q];
+        const uint32_t *jm = jmap_at(tm, s_jm, q);
+        const uint8_t *xi = (const uint8_t *)jm + c * ns;
+        const uint16_t *yi = (const uint16_t *)(jm + ((C * ns + 3) >> 2)) + (cup * C + c) * ns;
+        const uint64_t *ar = stg + off_a[q] + jr * tm.a[q].C;
+        const uint64_t *nr = stg + off_n[q] + (DENSE ? 0 : jr * tm.nt[q].C);
+        for (int j = 0; j < ns; j++) {
+          const uint64_t z = nr[yi[j]];
+          if (!z) continue;
+          const uint64_t xa = ar[xi[j]];
+          if (xa) add_ck(xq, mul_ck(xa, z, of), of);
+        }
+      } else {
+        xq = xp[q];
+        prd += 8;
+      }
+      if (xq) add_ck(y, mul_ck(tm.w[q], xq, of), of);
+    }
+    return y;
+  };
+  const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
+  if (DENSE) {
+    for (int64_t v = wave; v < grp.n_lim; v += nwave) {
+      uint64_t mt[NT], m = 0;
+#pragma unroll
+      for (int q = 0; q < NT; q++) {
+        mt[q] = tm.a[q].mask[v] & bmask;
+        m |= mt[q];
+      }
+      if (lane == 0) {
+        dst.mask[v] = m;
+        prd += 8 * (uint64_t)NT;
+        pwr += 8;
+      }
+      if (!m) continue;
+      const int cv = colr[v];
+      const int nrows = __popcll(m);
+      for (int j0 = 0; j0 < nrows; j0 += R) {
+        const bool act = jr < R && j0 + jr < nrows;
+        const int b = act ? nth_bit(m, j0 + jr) : 0;
+        const int64_t row = v * B + b;
+        uint32_t on = 0;
+        uint64_t xp[NT];
+#pragma unroll
+        for (int q = 0; q < NT; q++) {
+          xp[q] = 0;
+          const bool hq = act && ((mt[q] >> b) & 1ull);
+          on |= (uint32_t)hq << q;
+          if (hq && !tm.nt[q].val) xp[q] = tm.a[q].val[row * C + c];
+        }
+        if (j0 == 0) {
+#pragma unroll
+          for (int q = 0; q < NT; q++)
+            if (tm.nt[q].val)
+              for (int i = lane; i < tm.nt[q].C; i += 64) stg[off_n[q] + i] = tm.nt[q].val[v * tm.nt[q].C + i];
+        }
+#pragma unroll
+        for (int q = 0; q < NT; q++) {
+          if (!tm.nt[q].val) continue;
+          const int Cq = tm.a[q].C;
+          for (int i = lane; i < R * Cq; i += 64) {
+            const int r = i / Cq;
+            if (j0 + r >= nrows) break;
+            const int br = nth_bit(m, j0 + r);
+            if ((mt[q] >> br) & 1ull) stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
+          }
+        }
+        wave_lds_sync();
+        if (act) {
+          dst.val[row * C + c] = slot(b, v, on, xp, cv);
+          pwr += 8;
+        }
+        wave_lds_sync();  // the stage is read before the next chunk overwrites it
+      }
+    }
+  } else {
+    const int64_t N = *L.cnt, nch = (N + R - 1) / R;
+    for (int64_t ch = wave; ch < nch; ch += nwave) {
+      const int64_t e0 = ch * R;
+      const int lim = N - e0 < R ? (int)(N - e0) : R;  // entries of this chunk
+      const int64_t e = e0 + jr;
+      const bool act = jr < lim;
+      int64_t v = 0;
+      int b = 0, cv = 0;
+      uint64_t xp[NT];
+#pragma unroll
+      for (int q = 0; q < NT; q++) xp[q] = 0;
+      if (act) {
+        const int64_t x = L.list[e];
+        v = x >> 6;
+        b = (int)(x & 63);
+        cv = colr[v];
+#pragma unroll
+        for (int q = 0; q < NT; q++)
+          if (!tm.nt[q].val) xp[q] = tm.a[q].val[e * C + c];
+      }
+#pragma unroll
+      for (int q = 0; q < NT; q++) {
+        if (!tm.nt[q].val) continue;
+        const int Cq = tm.a[q].C, Cn = tm.nt[q].C;
+        for (int i = lane; i < lim * Cq; i += 64) stg[off_a[q] + i] = tm.a[q].val[e0 * Cq + i];
+        for (int i = lane; i < lim * Cn; i += 64) {
+          const int r = i / Cn;
+          const int64_t vr = L.list[e0 + r] >> 6;
+          stg[off_n[q] + i] = tm.nt[q].val[vr * Cn + (i - r * Cn)];
+        }
+      }
+      wave_lds_sync();
+      if (act) {
+        dst.val[e * C + c] = slot(b, v, (1u << NT) - 1u, xp, cv);
+        pwr += 8;
+      }
+      wave_lds_sync();
+    }
+  }
+  flag_trials(ovf, of ? 1ull : 0ull);
+  prof_flush(grp.prof, prd, pwr, 0);
+}
+
+template <bool DENSE>
+void launch_axpyn_rows_nt(int nt, dim3 gr, size_t lds, hipStream_t st, const GroupDev &grp, int64_t n,
+                          const uint8_t *colr, LevelDev L, const AxpyTerms &tm, RegDev dst, uint32_t *ovf,
+                          int jm_words, int words) {
+#define CC_AR(NTV)                                                                                                   \
+  hipLaunchKernelGGL((k_axpyn_rows<DENSE, NTV>), gr, dim3(BLK), lds, st, grp, n, colr, L, tm, dst, ovf, jm_words, \
+                     words)
+  switch (nt) {
+    case 1: CC_AR(1); break;
+    case 2: CC_AR(2); break;
+    case 3: CC_AR(3); break;
+    default: CC_AR(4); break;
+  }
+#undef CC_AR
+}
+
 // ------------------------------------------------------------------ root merge
 // count[t] += w * sum over entries (v, b) of both levels of
 //             sum over R of a[(v,b)][R] * b[(v,b)][K \ {chi u, chi v} \ R]
@@ -1637,14 +1834,6 @@ __global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, co
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (s_acc[2 * t] | s_acc[2 * t + 1]) atomic_add128(&acc.sum[2 * t], s_acc[2 * t], s_acc[2 * t + 1]);
   prof_flush(grp.prof, prd, 0, 0);
-}
-
-// Lanes of one wavefront see each other's LDS writes after this (the
-// wavefront's LDS operations have completed and are ordered before the reads).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // The same merge for one colouring, by chunks of rows: a wavefront takes R =
@@ -2501,6 +2690,27 @@ void launch_axpyn(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev 
   if (lds > NJMAP_LDS_MAX) {  // keep the LDS of one launch modest: no maps
     lds = 0;
     for (int q = 0; q < nterms; q++) tm.jm[q] = nullptr, tm.jmw[q] = tm.jns[q] = 0;
+  }
+  // one colouring, every NodeJoin term with its split map: chunks of rows
+  // staged in LDS per wavefront (CC_AXPY_ROWS=0: one slot per lane with gathers)
+  bool all_maps = true;
+  for (int q = 0; q < nterms; q++) all_maps = all_maps && (!tm.nt[q].val || tm.jmw[q]);
+  if (grp.T == 1 && dst.C <= 64 && all_maps && !getenv_flag_off("CC_AXPY_ROWS")) {
+    const int R = 64 / dst.C;
+    int words = 0;
+    for (int q = 0; q < nterms; q++)
+      if (tm.nt[q].val) words += R * tm.a[q].C + (grp.dense ? 1 : R) * tm.nt[q].C;
+    const int jm_words = (int)(lds / 4);
+    words = std::max(1, words);
+    const size_t lds2 = (size_t)(jm_words + 1) / 2 * 8 + (size_t)(BLK / 64) * words * 8;
+    if (words <= 2048 && lds2 <= 64 * 1024) {
+      const dim3 gr(grp.dense ? (unsigned)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536)) : 8192u);
+      if (grp.dense)
+        launch_axpyn_rows_nt<true>(nterms, gr, lds2, st, grp, n, colr, L, tm, dst, ovf, jm_words, words);
+      else
+        launch_axpyn_rows_nt<false>(nterms, gr, lds2, st, grp, n, colr, L, tm, dst, ovf, jm_words, words);
+      return;
+    }
   }
   if (grp.dense) {  // the activity word of dst is written by the same pass
     const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.n_lim + 3) / 4, 65536));

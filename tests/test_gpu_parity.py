@@ -101,6 +101,9 @@ ONE_TRIAL_MODES = {
     # the fused root merge with per-slot gathers instead of rows staged in LDS
     "dense-mroot-slots": {"CC_DENSE": "all", "CC_MROOT_ROWS": "0"},
     "sparse-mroot-slots": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_MROOT_ROWS": "0"},
+    # the AXPY chains one slot per lane with gathers instead of rows staged in LDS
+    "dense-axpy-slots": {"CC_DENSE": "all", "CC_AXPY_ROWS": "0"},
+    "sparse-axpy-slots": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_AXPY_ROWS": "0"},
 }
 
 
