@@ -893,18 +893,17 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
               const uint32_t Rp = spread2(s_um[co], cu, cw);
               if (!((Rp >> cv) & 1u)) continue;
               const uint32_t R = Rp & ~(1u << cv);
+              const int nR = __popc(R);
+              if (ra > nR) continue;
               uint64_t sum = 0;
-              uint32_t s1 = R;
-              for (;;) {
-                if (__popc(s1) == ra) {
-                  const uint64_t xa = row[s_rank[squeeze2(s1, cu, cv)]];
-                  if (xa) {
-                    const uint64_t y = er[s_rank[squeeze2(R & ~s1, cv, cw)]];
-                    if (y) add_ck(sum, mul_ck(xa, y, of), of);
-                  }
+              // the subsets of R of size ra (the input row's colours)
+              for (uint32_t cm = (1u << ra) - 1u; cm < (1u << nR); cm = ra ? next_comb(cm) : (1u << nR)) {
+                const uint32_t s1 = deposit(cm, R);
+                const uint64_t xa = row[s_rank[squeeze2(s1, cu, cv)]];
+                if (xa) {
+                  const uint64_t y = er[s_rank[squeeze2(R & ~s1, cv, cw)]];
+                  if (y) add_ck(sum, mul_ck(xa, y, of), of);
                 }
-                if (s1 == 0) break;
-                s1 = (s1 - 1) & R;
               }
               if (sum) add_ck(acc[co * NB + tid], sum, of);
             }
@@ -2281,6 +2280,147 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
   flag_trials(ovf, ofm);
 }
 
+// The same merge vertex-major: a wavefront owns a vertex x with all the
+// group's sources that have a row of a at x, reads x's neighbour list once
+// with each neighbour's source bits of b, and gives each lane one (neighbour,
+// trial, output slot): the lane sums its slot over the sources common to x
+// and its neighbour y, then adds the sum to the edge's slot once.  Rows are
+// found from the bits (dense: (v, b); sparse: the level's base and the
+// marks below b).  Requires T * C_out <= 64.
+template <bool DENSE>
+__global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev La,
+                                                 LevelDev Lb, RegDev a, RegDev bb, TabDev et, int e_src_first,
+                                                 int out_first_is_x, uint64_t w, uint64_t *out, int s_out, int C_out,
+                                                 uint32_t *ovf, const uint16_t *lut) {
+  __shared__ uint16_t s_rank[2048];
+  __shared__ uint32_t s_uo[64];  // unranked output slots
+  __shared__ int32_t s_u[WAVE];
+  __shared__ int32_t s_bnd[WAVE];
+  __shared__ uint8_t s_cu[WAVE * WAVE];
+  load_rank(s_rank, lut);
+  load_sources(grp, colr, g.n, s_u, s_cu);
+  for (int i = threadIdx.x; i < WAVE; i += blockDim.x) s_bnd[i] = i < grp.B ? (int32_t)vbound(grp, grp.src[i]) : -1;
+  for (int c = threadIdx.x; c < C_out; c += blockDim.x) s_uo[c] = unrank(lut, s_out - 2, c);
+  __syncthreads();
+  const int T = grp.T, B = grp.B, Ca = a.C, Cb = bb.C;
+  const int ra = a.s - 2, rb = bb.s - 2;
+  const int per = T * C_out, NY = 64 / per;  // neighbours per round
+  const int lane = threadIdx.x % 64;
+  const int yl = lane / per, r = lane - yl * per, t = r / C_out, c = r - t * C_out;
+  const bool lane_on = yl < NY;
+  const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
+  const int64_t n = g.n;
+  uint64_t ofm = 0;
+  const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
+  const int64_t nitems = DENSE ? grp.n_lim : (int64_t)La.cnt[1];
+  for (int64_t it = wave; it < nitems; it += nwave) {
+    const int x = DENSE ? (int)it : La.vlist[it];
+    uint64_t A;
+    int64_t abase = 0;
+    if (DENSE) {
+      A = a.mask[x] & bmask;
+    } else {
+      const ulonglong2 p = ((const ulonglong2 *)La.mb)[x];
+      A = p.x;
+      abase = (int64_t)p.y;
+    }
+    const uint64_t Aall = A;  // sparse: the entries of x are numbered over all its marks
+    // sources whose walks may pass x
+    A &= __ballot(lane < B && s_bnd[lane] > x);
+    if (!A) continue;
+    int umax = 0;
+    for (uint64_t q = A; q; q &= q - 1) umax = max(umax, s_bnd[__builtin_ctzll(q)]);
+    const int cx = colr[(int64_t)t * n + x];
+    const int64_t r0 = g.rp[x], r1 = g.rp[x + 1];
+    bool of = false;
+    for (int64_t j0 = r0; j0 < r1; j0 += 64) {
+      const int64_t ee = j0 + lane;
+      int y = ee < r1 ? g.col[ee] : VNONE;
+      if (y >= umax || (DENSE && y >= grp.n_lim)) y = VNONE;  // ascending: the later ones too
+      uint64_t Bm = 0;
+      int64_t bbase = 0;
+      if (y != VNONE) {
+        if (DENSE) {
+          Bm = bb.mask[y];
+        } else {
+          const ulonglong2 p = ((const ulonglong2 *)Lb.mb)[y];
+          Bm = p.x;
+          bbase = (int64_t)p.y;
+        }
+      }
+      const uint64_t Bfull = Bm;
+      Bm &= A;
+      uint64_t todo = __ballot(Bm != 0);
+      const bool stop = __ballot(y == VNONE) != 0;
+      while (todo) {
+        // this round: the next NY neighbours with common sources
+        int jn = -1;
+        uint64_t tcur = todo;
+        for (int i = 0; i < NY; i++) {
+          const int jj = tcur ? __builtin_ctzll(tcur) : -1;
+          if (i == yl) jn = jj;
+          if (tcur) tcur &= tcur - 1;
+        }
+        todo = tcur;
+        const int yv = __shfl(y, jn < 0 ? 0 : jn);
+        const uint64_t Bv = __shfl(Bm, jn < 0 ? 0 : jn), Bf = __shfl(Bfull, jn < 0 ? 0 : jn);
+        const int64_t bbv = __shfl(bbase, jn < 0 ? 0 : jn);
+        if (!lane_on || jn < 0) continue;
+        const int cy = colr[(int64_t)t * n + yv];
+        if (cy == cx) continue;
+        const uint32_t Rp = spread2(s_uo[c], cx, cy);
+        const int64_t es = j0 + jn;
+        const int64_t tslot = e_src_first ? es : g.rev[es];
+        const uint64_t *er = et.val ? et.val + (tslot * T + t) * et.C : nullptr;
+        uint64_t sum = 0;
+        for (uint64_t q = Bv; q; q &= q - 1) {
+          const int b = __builtin_ctzll(q);
+          if (yv >= s_bnd[b]) continue;
+          const int cu = s_cu[t * WAVE + b];
+          if (cu == cx || cu == cy || !((Rp >> cu) & 1u)) continue;
+          const uint32_t R = Rp & ~(1u << cu);
+          const uint64_t lowb = (1ull << b) - 1ull;
+          const int64_t ea = DENSE ? (int64_t)x * B + b : abase + __popcll(Aall & lowb);
+          const int64_t eb = DENSE ? (int64_t)yv * B + b : bbv + __popcll(Bf & lowb);
+          const uint64_t *ar = a.val + (ea * T + t) * Ca;
+          const uint64_t *br = bb.val + (eb * T + t) * Cb;
+          // R = s1 + s2 + Qe: the colours of a's row, of b's row and of the edge table's
+          const int nR = __popc(R);
+          if (ra > nR) continue;
+          for (uint32_t cm = (1u << ra) - 1u; cm < (1u << nR); cm = ra ? next_comb(cm) : (1u << nR)) {
+            const uint32_t s1 = deposit(cm, R);
+            const uint64_t xa = ar[s_rank[squeeze2(s1, cu, cx)]];
+            if (!xa) continue;
+            const uint32_t Q = R & ~s1;
+            const int nQ = nR - ra;
+            if (!er) {  // no edge table: b's row takes all of Q
+              if (nQ != rb) continue;
+              const uint64_t xb = br[s_rank[squeeze2(Q, cu, cy)]];
+              if (xb) add_ck(sum, mul_ck(xa, xb, of), of);
+              continue;
+            }
+            if (rb > nQ) continue;
+            for (uint32_t cq = (1u << rb) - 1u; cq < (1u << nQ); cq = rb ? next_comb(cq) : (1u << nQ)) {
+              const uint32_t s2 = deposit(cq, Q);
+              const uint64_t xb = br[s_rank[squeeze2(s2, cu, cy)]];
+              if (!xb) continue;
+              const uint64_t xe = er[s_rank[squeeze2(Q & ~s2, cx, cy)]];
+              if (xe) add_ck(sum, mul_ck(mul_ck(xa, xb, of), xe, of), of);
+            }
+          }
+        }
+        if (sum) {
+          const int64_t oslot = out_first_is_x ? es : g.rev[es];
+          atomic_add_ck(&out[(oslot * T + t) * C_out + c], mul_ck(sum, w, of), of);
+        }
+      }
+      if (stop) break;
+    }
+    if (of) ofm |= 1ull << t;
+  }
+  flag_trials(ovf, ofm);
+}
+
 // T[u,y] += w * A[u][Ra] * E(u,y)[Re] * b[(y,b)][R2] over the lower neighbours y of u_b.
 __global__ __launch_bounds__(BLK) void k_medge_t(GraphDev g, GroupDev grp, const uint8_t *colr,
                                                  const int32_t *lowcnt, int max_low, TabDev nt, LevelDev Lb,
@@ -2813,6 +2953,17 @@ void launch_munary(const GroupDev &grp, int64_t n, const uint8_t *colr, LevelDev
 void launch_medge(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev La, LevelDev Lb, RegDev a,
                   RegDev b, TabDev etab, int e_src_first, int out_first_is_x, uint64_t w, uint64_t *out, int s_out,
                   int C_out, uint32_t *ovf, hipStream_t st) {
+  // vertex-major (CC_MEDGE_V=0: one thread per (entry, trial, slot), each scanning the neighbour list)
+  if ((int64_t)grp.T * C_out <= 64 && !getenv_flag_off("CC_MEDGE_V")) {
+    const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((grp.dense ? grp.n_lim : 65536) / 4 + 1, 65536));
+    if (grp.dense)
+      hipLaunchKernelGGL(k_medge_v<true>, dim3(gr), dim3(BLK), 0, st, g, grp, colr, La, Lb, a, b, etab, e_src_first,
+                         out_first_is_x, w, out, s_out, C_out, ovf, cur_lut());
+    else
+      hipLaunchKernelGGL(k_medge_v<false>, dim3(gr), dim3(BLK), 0, st, g, grp, colr, La, Lb, a, b, etab, e_src_first,
+                         out_first_is_x, w, out, s_out, C_out, ovf, cur_lut());
+    return;
+  }
   hipLaunchKernelGGL(k_medge, dim3(fgrid(grp, (int64_t)grp.T * C_out)), dim3(BLK), 0, st, g, grp, colr, La, Lb, a, b,
                      etab, e_src_first, out_first_is_x, w, out, s_out, C_out, ovf, cur_lut());
 }

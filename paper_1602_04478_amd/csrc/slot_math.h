@@ -40,6 +40,23 @@ __device__ __forceinline__ uint32_t unrank(const uint16_t *lut, int r, int idx) 
   return lut[LUT_UNRANK + lut[LUT_OFF + r] + idx];
 }
 
+// The bits of x placed at the set bits of m, lowest first (parallel deposit).
+__device__ __forceinline__ uint32_t deposit(uint32_t x, uint32_t m) {
+  uint32_t r = 0;
+  for (; m && x; x >>= 1) {
+    const uint32_t low = m & (0u - m);
+    if (x & 1u) r |= low;
+    m ^= low;
+  }
+  return r;
+}
+// The next larger integer with the same number of set bits (x > 0): with
+// deposit() it walks the subsets of a given size of a mask in order.
+__device__ __forceinline__ uint32_t next_comb(uint32_t x) {
+  const uint32_t c = x & (0u - x), r = x + c;
+  return (((r ^ x) >> 2) >> __builtin_ctz(c)) | r;
+}
+
 // acc += a (checked)
 __device__ __forceinline__ void add_ck(uint64_t &acc, uint64_t a, bool &of) {
   uint64_t s = acc + a;

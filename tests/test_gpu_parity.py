@@ -52,6 +52,9 @@ PATH_MODES = {
     # root merges read their AXPY chain as stored rows (the chain not summed inside the merge)
     "nofuseroot-dense": {"CC_DENSE": "all", "CC_FUSE_ROOT": "0"},
     "nofuseroot-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_FUSE_ROOT": "0"},
+    # merges into edge tables one thread per (entry, trial, slot) instead of vertex-major
+    "medge-slots-dense": {"CC_DENSE": "all", "CC_MEDGE_V": "0"},
+    "medge-slots-sparse": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_MEDGE_V": "0"},
 }
 
 
