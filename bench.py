@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
     ap.add_argument("--batch-trials", type=int, default=8,
                     help="colourings solved plain and in one batched call (0: skip this comparison)")
+    ap.add_argument("--legs", default="c3,c4",
+                    help="extra legs of the default run (comma-separated; 'none' for none): c3 = domino+tail on the "
+                         "Chung-Lu n=2e6 graph, plain against batched; c4 = 20 generated queries batched against plain")
+    ap.add_argument("--c3-trials", type=int, default=2)
+    ap.add_argument("--c4-n", type=int, default=50_000)
+    ap.add_argument("--c4-trials", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run four copies of 1 GiB on the device, so that hardware byte counters "
                          "collected over this run can be scaled against a kernel of known traffic")
@@ -222,39 +228,77 @@ def c1_one_thread_seconds():
         return None
 
 
-def run_uneven(a):
+def uneven_leg(n, T):
     """Batched uneven queries: 20 generated treewidth-2 queries of 4-10 nodes
-    (query seed 204), 16 colourings each, on a Chung-Lu graph (mean 20,
-    exponent 2.1, structural cutoff, seed 4) of --uneven-n vertices: one
-    cc_count_batch call (trial-group size tuned online per query, launch
-    sequences replayed from hipGraphs) against plain per-colouring calls."""
+    (query seed 204), T colourings each, on a Chung-Lu graph (mean 20,
+    exponent 2.1, structural cutoff, seed 4) of n vertices: one cc_count_batch
+    call (trial-group size and tree tuned online per query, launch sequences
+    replayed from hipGraphs, queries side by side on worker streams) against
+    plain per-colouring calls; neither profiled."""
     from cc_inputs import graphs, queries as Q
     from paper_1602_04478_amd import cc
-    g = graphs.chung_lu(a.uneven_n, 20.0, 2.1, None, seed=4)
+    g = graphs.chung_lu(n, 20.0, 2.1, None, seed=4)
     dg = cc.Graph.from_csr(g)
     qs = [cc.Query(k, E) for k, E, fam in Q.random_queries(204, 20, 4, 10)]
     seeds = [204 + i for i in range(len(qs))]
-    T = a.uneven_trials
     cc.count_batch(dg, qs[:1], seeds[:1], [2])  # warm-up
     t0 = time.perf_counter()
     counts, ovf, est = cc.count_batch(dg, qs, seeds, [T] * len(qs))
     t_batch = time.perf_counter() - t0
-    print(f"[bench] uneven batched: {t_batch:.2f} s", file=sys.stderr, flush=True)
+    print(f"[bench] uneven queries n={n}: batched {t_batch:.2f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     plain = []
     for q, sd in zip(qs, seeds):
         for t in range(T):
             plain.append(int(cc.count(dg, q, sd + t, 1)[0][0]))
     t_plain = time.perf_counter() - t0
+    print(f"[bench] uneven queries n={n}: plain {t_plain:.2f} s", file=sys.stderr, flush=True)
     col = len(qs) * T
+    return {"workload": f"uneven queries: Chung-Lu n={g.n} m={g.m} (mean 20, exponent 2.1), 20 generated queries "
+                        f"of 4-10 nodes x {T} colourings, one batched call",
+            "value": col * g.m / t_batch, "unit": "colourings*edges/s", "seconds": t_batch,
+            "plain_value": col * g.m / t_plain, "plain_seconds": t_plain, "speedup_vs_plain": t_plain / t_batch,
+            "counts_match_plain": [int(c) for c in counts] == plain, "overflowed": int(ovf.sum())}
+
+
+def c3_leg(T):
+    """The C3 shape at full size (Chung-Lu n = 2e6, mean 20, exponent 2.2,
+    structural cutoff, seed 3; domino + tail, k = 8): T colourings as T plain
+    calls and as one batched call, neither profiled; counts must agree."""
+    from cc_inputs import graphs, queries as Q
+    from paper_1602_04478_amd import cc
+    t0 = time.perf_counter()
+    g = graphs.workload_graph("cl2m")
+    print(f"[bench] c3 graph: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    k, E = Q.domino_tail()
+    dg, q = cc.Graph.from_csr(g), cc.Query(k, E)
+    pl, tp = [], []
+    for t in range(T):
+        t1 = time.perf_counter()
+        pl.append(cc.count(dg, q, 103 + t, 1))
+        tp.append(time.perf_counter() - t1)
+        print(f"[bench] c3 plain colouring {t}: {tp[-1]:.2f} s", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    bc, bo, be = cc.count_batch(dg, [q], [103], [T])
+    dt = time.perf_counter() - t1
+    print(f"[bench] c3 batched ({T} colourings): {dt:.2f} s", file=sys.stderr, flush=True)
+    rep = cc.last_tune_report()
+    return {"workload": f"cl2m: n={g.n} m={g.m} maxdeg={int(g.degrees().max())}; query domino+tail; k=8; "
+                        f"{T} colourings (seed 103)",
+            "value": T * g.m / dt, "unit": "colourings*edges/s", "seconds": dt, "trial_group": rep["trial_group"],
+            "plain_value": T * g.m / sum(tp), "plain_seconds_per_colouring": tp, "speedup_vs_plain": sum(tp) / dt,
+            "counts": [[int(bc[t]), int(bo[t])] for t in range(T)],
+            "counts_match_plain": all(int(bc[t]) == int(pl[t][0][0]) and int(bo[t]) == int(pl[t][1][0])
+                                      for t in range(T))}
+
+
+def run_uneven(a):
+    leg = uneven_leg(a.uneven_n, a.uneven_trials)
     out = {"metric": "colourings*data-edges/sec (exact uint64 colourful counts)",
-           "value": col * g.m / t_batch, "unit": "colourings*edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-           "ms_per_step": 1000 * t_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "u64", "data": "synthetic",
-           "config": {"workload": f"uneven queries: Chung-Lu n={g.n} m={g.m}, 20 generated queries of 4-10 nodes "
-                                  f"x {T} colourings, one batched call"},
-           "plain_value": col * g.m / t_plain, "speedup_vs_plain": t_plain / t_batch,
-           "counts_match_plain": [int(c) for c in counts] == plain, "overflowed": int(ovf.sum())}
+           "value": leg["value"], "unit": "colourings*edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": 1000 * leg["seconds"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64", "data": "synthetic", "config": {"workload": leg["workload"]},
+           **{k: v for k, v in leg.items() if k not in ("workload", "value", "unit", "seconds")}}
     print(json.dumps(out))
 
 
@@ -601,6 +645,11 @@ def main():
                                "mismatches": len(bad), "device_total_equals_step0": int(ex[0]) == results[0][0],
                                "shares_sum_to_total": sum(int(x) for x in per[0]) == int(ex[0])}
     out["graph_gen_s"] = t_gen
+    legs = [] if a.legs == "none" or a.workload != "cl1m" else a.legs.split(",")
+    if "c3" in legs:
+        out["c3_leg"] = c3_leg(a.c3_trials)
+    if "c4" in legs:
+        out["c4_leg"] = uneven_leg(a.c4_n, a.c4_trials)
     print(json.dumps(out))
 
 
