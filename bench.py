@@ -77,7 +77,7 @@ def query_of(name):
 
 
 KERNEL_OF = {  # profiled op name -> the HIP kernel that runs it
-    "edgejoin": "k_ejv", "nodejoin": "k_nj", "axpy": "k_axpyn", "merge_root": "k_mroot", "init": "k_init",
+    "edgejoin": "k_ejv", "edgejoin2": "k_ejv", "nodejoin": "k_nj", "axpy": "k_axpyn", "merge_root": "k_mroot", "init": "k_init",
     "merge_u": "k_munary", "merge_v": "k_munary", "merge_edge": "k_medge", "merge_edge_t": "k_medge_t",
     "level_build_sparse": "level build", "light": "k_light", "light_large": "k_light", "leaf": "k_leaf",
     "root_single": "k_root_single", "merge_root_terms": "k_mroot_terms", "merge_pair": "k_mpair",
@@ -128,9 +128,11 @@ def roofline(tstats, cstats, workload):
         kern[op] = {"kernel": kn, "launches": launches, "ms": 1000.0 * secs, "alg_GB_per_launch": bpl / 1e9,
                     "alg_GBps": bpl * launches / secs / 1e9 if secs > 0 and bpl > 0 else None}
         if op.startswith("edgejoin") and cl:
+            # two EdgeJoins on one scan ("edgejoin2") count slots instead of rows
+            unit = "slots" if op.startswith("edgejoin2") else "rows"
             kern[op]["per_launch_triples_scanned"] = cw[0] / cl
-            kern[op]["per_launch_rows_relaxed"] = cw[1] / cl
-            kern[op]["per_launch_rows_written"] = cw[2] / cl
+            kern[op][f"per_launch_{unit}_relaxed"] = cw[1] / cl
+            kern[op][f"per_launch_{unit}_written"] = cw[2] / cl
     name = max(per_kernel, key=lambda x: per_kernel[x][1])
     launches, secs, byts, ops = per_kernel[name]
     ach = byts / secs / 1e9 if secs > 0 else 0.0

@@ -313,6 +313,15 @@ void give_event(hipEvent_t e) {
   g_ev_pool.push_back(e);
 }
 
+// CC_PROFILE_BY_OP=1: one profile record per operation of a program
+static bool by_op() {
+  static const bool on = [] {
+    const char *ev = getenv("CC_PROFILE_BY_OP");
+    return ev && *ev == '1';
+  }();
+  return on;
+}
+
 struct Profiler {
   bool on = false, counting = false;
   hipStream_t st;
@@ -356,6 +365,14 @@ struct Profiler {
     r.fixed = 0;
     recs.push_back(r);
     return c;
+  }
+  // forget the current record (nothing was launched for it)
+  void drop() {
+    if (!on || recs.empty()) return;
+    give_event(recs.back().a);
+    give_event(recs.back().b);
+    if (recs.back().ctr == nctr - 1 && nctr > 0) nctr--;
+    recs.pop_back();
   }
   // the current record's operation name (a launch that turned out to be another kind)
   void rename(const std::string &nm) {
@@ -1266,13 +1283,35 @@ void Solver::run_group(size_t bi, const Program &P, const Grp &G, int Tg, uint64
       if (prof) prof->end();
       continue;
     }
+    // two data-edge EdgeJoins in a row from the same level (the second not
+    // reading the first's output): one launch over one neighbour scan
+    if (op.kind == OP_EJ && op.tab < 0) {
+      const size_t si = (size_t)(&stp - steps.data());
+      if (si + 1 < steps.size() && !steps[si + 1].fused) {
+        const Op &o2 = P.ops[steps[si + 1].op];
+        if (o2.kind == OP_EJ && o2.tab < 0 && o2.a != op.dst && o2.dst != op.a && o2.dst != op.dst &&
+            P.reg_depth[o2.a] == P.reg_depth[op.a]) {
+          if (prof) {
+            std::string nm = std::string("edgejoin2") + (G.dense ? "_dense" : "_sparse");
+            if (by_op()) nm += "_op" + std::to_string(stp.op) + "+" + std::to_string(steps[si + 1].op);
+            // counted in slots: 8 B per input slot relaxed, 8 B per slot written
+            grp.prof = prof->begin(nm.c_str(), true, 4.0, 8.0, 8.0 * Tg);
+          }
+          if (launch_ej_dual(gd_, grp, colr, lv(op.a), lv(op.dst), regdev(op.a), regdev(op.dst), regdev(o2.a),
+                             regdev(o2.dst), ovf, st)) {
+            HIP_CHECK(hipGetLastError());
+            if (prof) prof->end();
+            skip_until = si + 2;
+            continue;
+          }
+          if (prof) prof->drop();
+          grp.prof = nullptr;
+        }
+      }
+    }
     if (prof) {
       std::string nm = std::string(names[op.kind]) + (G.dense ? "_dense" : "_sparse");
-      static const bool by_op = [] {
-        const char *ev = getenv("CC_PROFILE_BY_OP");
-        return ev && *ev == '1';
-      }();
-      if (by_op) nm += "_op" + std::to_string(stp.op);  // one record per operation of the program
+      if (by_op()) nm += "_op" + std::to_string(stp.op);  // one record per operation of the program
       if (op.kind == OP_EJ) {
         // algorithmic bytes: a 4-byte neighbour id per scanned pair, an
         // input row (plus the annotated edge's table row) per relaxation,

@@ -572,7 +572,13 @@ constexpr size_t EJV_LDS_MAX = 56 * 1024;
 // a step of SW neighbours that relax a row are numbered by an exclusive scan
 // of their counts, and each lane takes one pair a round, adding into the
 // source's column with LDS atomics (checked through the returned old value).
-template <bool ANN, int SW, bool EPI, int NB, bool MAP, bool PACK = false>
+//
+// With DUAL (packed only) the launch also runs a second EdgeJoin whose input
+// register epi.in2 lies at the same level as a: both share the neighbour scan
+// (the lists, the activity words or marks, the colours), a pair names its
+// input, and the second output is epi.regs[1] in the LDS columns after the
+// first's.  The profile counts slots instead of rows.
+template <bool ANN, int SW, bool EPI, int NB, bool MAP, bool PACK = false, bool DUAL = false>
 __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK ? EJ_MINW_PD : EJ_MINW_DENSE) : 1) void k_ejv(GraphDev g, GroupDev grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                                               const Epilogue epi, TabDev et, int e_src_first, uint32_t *ovf,
                                               AccDev accd, const uint16_t *lut, const uint32_t *emap, int emap_w,
@@ -609,6 +615,10 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
   uint32_t *const s_map = (uint32_t *)((char *)accs + ejv_lds(epi.ncols, epi.nregs, EPI, NB));
   if (MAP)
     for (int i = tid; i < emap_w; i += NB) s_map[i] = emap[i];
+  uint32_t *const s_map2 = s_map + emap_w;  // DUAL: the second input's map
+  if (DUAL)
+    for (int i = tid; i < epi.map2_w; i += NB) s_map2[i] = epi.map2[i];
+  const int Ca2 = DUAL ? epi.in2.C : 0, col2 = DUAL ? epi.regs[1].col : 0;
   __shared__ uint64_t s_cm[16];  // PACK: the sources of each colour (bit b: source b)
   __shared__ uint8_t s_cu[WAVE];  // PACK: source b's colour
   if (PACK) {
@@ -703,16 +713,18 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
         const int64_t ee = j0 + gl;
         int vj = ee < r1 ? g.col[ee] : VNONE;
         if (vj >= umax) vj = VNONE;
-        uint64_t inb = 0, mfull = 0;
+        uint64_t inb = 0, mfull = 0, inb2 = 0;
         int64_t bj = 0;
         if (vj != VNONE) {
           if (grp.dense) {
             inb = a.mask[vj];
+            if (DUAL) inb2 = epi.in2.mask[vj] & pass;
           } else {
             const ulonglong2 p = ((const ulonglong2 *)Lin.mb)[vj];
             mfull = p.x;
             bj = (int64_t)p.y;
             inb = mfull;
+            if (DUAL) inb2 = mfull & pass;
           }
           inb &= pass;
         }
@@ -720,7 +732,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
           // (key, trial, lower neighbour) triples: the pass's sources b with an
           // input row at v = vj (bit set in inb), v below u_b, and a trial in
           // which b is not idle at w (its colour differs from w's)
-          for (uint64_t r = inb; r; r &= r - 1) {
+          for (uint64_t r = inb | inb2; r; r &= r - 1) {
             const int uq = s_src[__builtin_ctzll(r)];
             if (vj < s_bnd[__builtin_ctzll(r)])
               for (int t = 0; t < T; t++) n_scan += colr[(int64_t)t * n + uq] != colr[(int64_t)t * n + w] ? 1u : 0u;
@@ -729,18 +741,20 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
         uint64_t todo = gballot(inb != 0);
         const bool stop = gballot(vj == VNONE) != 0;
         // one trial: the neighbour's colour travels with it (loaded by its own lane)
-        const int cvj = (T == 1 && inb) ? colr[vj] : 0;
+        const int cvj = (T == 1 && (inb | inb2)) ? colr[vj] : 0;
         if (PACK) {
           // sources that relax a row from neighbour j: bit set in inb, colour
           // neither the neighbour's nor w's (w's colour: the source is idle at w)
           const int cwv = colr[w];
           const uint64_t valid = (inb && cvj != cwv) ? inb & ~s_cm[cvj] & ~s_cm[cwv] : 0ull;
-          int incl = __popcll(valid);
+          const uint64_t valid2 = (DUAL && inb2 && cvj != cwv) ? inb2 & ~s_cm[cvj] & ~s_cm[cwv] : 0ull;
+          const int own = __popcll(valid) + (DUAL ? __popcll(valid2) : 0);
+          int incl = own;
           for (int o = 1; o < SW; o <<= 1) {
             const int y = __shfl_up(incl, o, SW);
             if (gl >= o) incl += y;
           }
-          const int excl = incl - __popcll(valid), P = __shfl(incl, SW - 1, SW);
+          const int excl = incl - own, P = __shfl(incl, SW - 1, SW);
           for (int p0 = 0; p0 < P; p0 += SW) {
             const int pp = p0 + gl;
             int jl = 0;  // the last neighbour whose first pair is at or before pp
@@ -749,23 +763,30 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
             const int kth = pp - __shfl(excl, jl, SW);
             const int vA = __shfl(vj, jl, SW), cA = __shfl(cvj, jl, SW);
             const uint64_t vm = __shfl(valid, jl, SW);
+            const uint64_t vm2 = DUAL ? __shfl(valid2, jl, SW) : 0ull;
             // (packed launches: whole wavefronts for dense groups, quarters for sparse ones)
             constexpr bool PD = SW == WAVE;
             const uint64_t mfA = PD ? 0 : __shfl(mfull, jl, SW);
             const int64_t bA = PD ? 0 : __shfl(bj, jl, SW);
             if (pp >= P) continue;
-            const int bb = nth_set_bit(vm, kth);
+            // the pair's input: the first register's pairs of a neighbour come first
+            const int n1 = DUAL ? __popcll(vm) : 0;
+            const bool sec = DUAL && kth >= n1;
+            const int bb = sec ? nth_set_bit(vm2, kth - n1) : nth_set_bit(vm, kth);
             if (vA >= s_bnd[bb]) continue;
-            n_rows++;
+            const int Cq = sec ? Ca2 : Ca;
+            n_rows += DUAL ? (uint32_t)Cq : 1u;
             const uint64_t below_bb = (1ull << bb) - 1ull;
-            const int colw = (tid - gl) + __popcll(pass & below_bb);  // the lane of source bb
-            const uint64_t *row = a.val + (PD ? (int64_t)vA * B + bb : bA + __popcll(mfA & below_bb)) * Ca;
-            const uint32_t *mA = s_map + ((s_cu[bb] * grp.k + cA) * grp.k + cwv) * (emap_cp >> 2);
+            const int colw = (tid - gl) + __popcll(pass & below_bb) + (sec ? col2 * NB : 0);  // source bb's column
+            const int64_t rid = PD ? (int64_t)vA * B + bb : bA + __popcll(mfA & below_bb);
+            const uint64_t *row = sec ? epi.in2.val + rid * Ca2 : a.val + rid * Ca;
+            const uint32_t *mA = sec ? s_map2 + ((s_cu[bb] * grp.k + cA) * grp.k + cwv) * (epi.map2_cp >> 2)
+                                     : s_map + ((s_cu[bb] * grp.k + cA) * grp.k + cwv) * (emap_cp >> 2);
             constexpr int UP = PD ? EJ_UNROLL_PD : EJ_UNROLL_P;
-            for (int c0 = 0; c0 < Ca; c0 += UP) {
+            for (int c0 = 0; c0 < Cq; c0 += UP) {
               uint64_t xa[UP];
 #pragma unroll
-              for (int q = 0; q < UP; q++) xa[q] = c0 + q < Ca ? row[c0 + q] : 0;
+              for (int q = 0; q < UP; q++) xa[q] = c0 + q < Cq ? row[c0 + q] : 0;
 #pragma unroll
               for (int q = 0; q < UP; q++) {
                 if (!xa[q]) continue;
@@ -1022,7 +1043,7 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
           }
         }
         // rows (w, b) written, all their trials (a hub's rows once, by its first chunk)
-        if (b >= 0 && lt == 0 && (split ? first_chunk : wr)) n_ent++;
+        if (b >= 0 && lt == 0 && (split ? first_chunk : wr)) n_ent += DUAL ? (uint32_t)Cj : 1u;
       }
     }
     if (gl == 0 && grp.dense)
@@ -2790,6 +2811,51 @@ void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, Leve
   else
     hipLaunchKernelGGL(k_ej<false>, dim3(gr), dim3(WAVE), lds, st, g, grp, colr, Lin, Lout, a, dst, etab,
                        e_src_first, ovf, cur_lut());
+}
+
+bool launch_ej_dual(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout,
+                    RegDev a1, RegDev d1, RegDev a2, RegDev d2, uint32_t *ovf, hipStream_t st) {
+  if (grp.T != 1 || grp.k > 16 || getenv_flag_off("CC_EJPACK") || getenv_flag_off("CC_EJMAP") ||
+      getenv_flag_off("CC_EJDUAL"))
+    return false;
+  if (!grp.dense && grp.T > 16) return false;
+  const uint32_t *m1 = nullptr, *m2 = nullptr;
+  int w1 = 0, cp1 = 0, w2 = 0, cp2 = 0;
+  if (!ejmap_find(grp.k, a1.s - 2, a1.C, &m1, &w1, &cp1) || !ejmap_find(grp.k, a2.s - 2, a2.C, &m2, &w2, &cp2))
+    return false;
+  if (d1.C + d2.C > VMAX_C) return false;
+  const size_t lds = ejv_lds(d1.C + d2.C, 2, false, EJ_BLK) + (size_t)(w1 + w2) * 4;
+  if (lds > EJV_LDS_MAX) return false;
+  Epilogue epi{};
+  epi.nops = 0;
+  epi.nregs = 2;
+  epi.ncols = d1.C + d2.C;
+  epi.regs[0] = EpiReg{d1, Lout, 0, 1};
+  epi.regs[1] = EpiReg{d2, Lout, d1.C, 1};
+  epi.in2 = a2;
+  epi.map2 = m2;
+  epi.map2_w = w2;
+  epi.map2_cp = cp2;
+  if (grp.dense && grp.nh > 0 && grp.split_lo < grp.n_lim) {
+    // the hubs' rows and activity words start at zero: their chunks add into them
+    for (const RegDev *d : {&d1, &d2}) {
+      const int64_t per = (int64_t)grp.B * grp.T * d->C;
+      launch_fill_u64(d->val + grp.split_lo * per, (grp.n_lim - grp.split_lo) * per, st);
+      launch_fill_u64(d->mask + grp.split_lo, grp.n_lim - grp.split_lo, st);
+    }
+  }
+  const int vpw = grp.dense ? 1 : WAVE / EJ_PACK_SW;
+  const int64_t nw = (grp.n_lim + vpw - 1) / vpw;
+  const int gr = (int)std::max<int64_t>(1, std::min<int64_t>((nw + EJ_BLK / WAVE - 1) / (EJ_BLK / WAVE),
+                                                             32768 / (EJ_BLK / WAVE)));
+  const AccDev acc{nullptr, nullptr, nullptr};
+  if (grp.dense)
+    hipLaunchKernelGGL((k_ejv<false, 64, false, EJ_BLK, true, true, true>), dim3(gr), dim3(EJ_BLK), lds, st, g, grp,
+                       colr, Lin, a1, epi, TabDev{nullptr, 0, 0}, 0, ovf, acc, cur_lut(), m1, w1, cp1);
+  else
+    hipLaunchKernelGGL((k_ejv<false, EJ_PACK_SW, false, EJ_BLK, true, true, true>), dim3(gr), dim3(EJ_BLK), lds, st, g,
+                       grp, colr, Lin, a1, epi, TabDev{nullptr, 0, 0}, 0, ovf, acc, cur_lut(), m1, w1, cp1);
+  return true;
 }
 
 void launch_nj(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev L, RegDev a, RegDev dst,

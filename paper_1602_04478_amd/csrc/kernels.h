@@ -112,6 +112,11 @@ struct Epilogue {
   int nops, nregs, ncols;
   EpiOp ops[EPI_MAX_OPS];
   EpiReg regs[EPI_MAX_REGS];
+  // a second EdgeJoin on the same scan (packed launches only): input in2 at
+  // the same level as the first input, output regs[1], slot map map2
+  RegDev in2;
+  const uint32_t *map2;
+  int map2_w, map2_cp;
 };
 
 const uint16_t *lut_device(int device);
@@ -146,6 +151,11 @@ void launch_init(const GraphDev &g, const GroupDev &grp, const int32_t *lowcnt, 
                  LevelDev L, RegDev dst, TabDev etab, int e_src_first, TabDev ntab, uint32_t *ovf, hipStream_t st);
 void launch_ej(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout, RegDev a,
                RegDev dst, TabDev etab, int e_src_first, uint32_t *ovf, hipStream_t st);
+// Two data-edge EdgeJoins a1 -> d1 and a2 -> d2 whose inputs share a level, in
+// one packed launch over one neighbour scan (one colouring); false when that
+// launch does not apply (then nothing was launched)
+bool launch_ej_dual(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, LevelDev Lout,
+                    RegDev a1, RegDev d1, RegDev a2, RegDev d2, uint32_t *ovf, hipStream_t st);
 // EdgeJoin with a fused epilogue (vertex-major kernel only; see epi_fits)
 void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
                    const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st);

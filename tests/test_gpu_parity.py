@@ -101,6 +101,9 @@ ONE_TRIAL_MODES = {
     "dense-unpacked": {"CC_DENSE": "all", "CC_EJPACK": "0"},
     "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
     "sparse-unpacked": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJPACK": "0"},
+    # every EdgeJoin launched on its own (no two sharing a neighbour scan)
+    "dense-nodual": {"CC_DENSE": "all", "CC_EJDUAL": "0"},
+    "sparse-nodual": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJDUAL": "0"},
     # the fused root merge with per-slot gathers instead of rows staged in LDS
     "dense-mroot-slots": {"CC_DENSE": "all", "CC_MROOT_ROWS": "0"},
     "sparse-mroot-slots": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_MROOT_ROWS": "0"},
