@@ -2823,7 +2823,13 @@ bool launch_ej_dual(const GraphDev &g, const GroupDev &grp, const uint8_t *colr,
   int w1 = 0, cp1 = 0, w2 = 0, cp2 = 0;
   if (!ejmap_find(grp.k, a1.s - 2, a1.C, &m1, &w1, &cp1) || !ejmap_find(grp.k, a2.s - 2, a2.C, &m2, &w2, &cp2))
     return false;
-  if (d1.C + d2.C > VMAX_C) return false;
+  // the LDS columns of both outputs bound the wavefronts per compute unit: a
+  // pair with many output slots runs as two launches (CC_EJDUAL_COLS: the limit)
+  static const int max_cols = [] {
+    const char *ev = getenv("CC_EJDUAL_COLS");
+    return ev ? atoi(ev) : 16;
+  }();
+  if (d1.C + d2.C > std::min(max_cols, VMAX_C)) return false;
   const size_t lds = ejv_lds(d1.C + d2.C, 2, false, EJ_BLK) + (size_t)(w1 + w2) * 4;
   if (lds > EJV_LDS_MAX) return false;
   Epilogue epi{};
