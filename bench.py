@@ -106,46 +106,52 @@ def traffic_record(kernel, workload):
     return rec["hbm_bytes_per_launch"]
 
 
-def roofline(tstats, cstats, workload):
-    """The dominant kernel (largest summed time over the timed steps, timed
-    with HIP events on the library's stream) against the HBM peak.
+def roofline(tstats, pstats, cstats, workload):
+    """The dominant kernel against the HBM peak.
 
-    tstats: the timed steps (event timing only); cstats: one untimed solve of
-    the first step's colouring with the kernels' algorithmic-byte counters on.
-    Bytes per launch of each operation come from cstats, launch durations from
-    tstats."""
-    per_kernel = {}
-    kern = {}
-    for op, (launches, secs, _b, _w) in tstats.items():
-        cl, _cs, cb, cw = cstats.get(op, (0, 0.0, 0.0, (0, 0, 0)))
-        bpl = cb / cl if cl else 0.0
-        kn = kernel_of(op)
-        a = per_kernel.setdefault(kn, [0, 0.0, 0.0, []])
-        a[0] += launches
-        a[1] += secs
-        a[2] += bpl * launches
-        a[3].append(op)
-        kern[op] = {"kernel": kn, "launches": launches, "ms": 1000.0 * secs, "alg_GB_per_launch": bpl / 1e9,
-                    "alg_GBps": bpl * launches / secs / 1e9 if secs > 0 and bpl > 0 else None}
-        if op.startswith("edgejoin") and cl:
-            # two EdgeJoins on one scan ("edgejoin2") count slots instead of rows
-            unit = "slots" if op.startswith("edgejoin2") else "rows"
-            kern[op]["per_launch_triples_scanned"] = cw[0] / cl
-            kern[op][f"per_launch_{unit}_relaxed"] = cw[1] / cl
-            kern[op][f"per_launch_{unit}_written"] = cw[2] / cl
+    tstats: the timed steps, HIP events on the library's stream around the
+    EdgeJoin launches only; pstats: one untimed solve with every launch
+    event-timed (the split over kernels, and which kernel dominates); cstats:
+    one untimed solve of the first step's colouring with the kernels'
+    algorithmic-byte counters on.  Bytes per launch of each operation come
+    from cstats; the dominant kernel's launch durations from tstats."""
+    def per_kernel_of(stats):
+        per_kernel, kern = {}, {}
+        for op, (launches, secs, _b, _w) in stats.items():
+            cl, _cs, cb, cw = cstats.get(op, (0, 0.0, 0.0, (0, 0, 0)))
+            bpl = cb / cl if cl else 0.0
+            kn = kernel_of(op)
+            a = per_kernel.setdefault(kn, [0, 0.0, 0.0, []])
+            a[0] += launches
+            a[1] += secs
+            a[2] += bpl * launches
+            a[3].append(op)
+            kern[op] = {"kernel": kn, "launches": launches, "ms": 1000.0 * secs, "alg_GB_per_launch": bpl / 1e9,
+                        "alg_GBps": bpl * launches / secs / 1e9 if secs > 0 and bpl > 0 else None}
+            if op.startswith("edgejoin") and cl:
+                # two EdgeJoins on one scan ("edgejoin2") count slots instead of rows
+                unit = "slots" if op.startswith("edgejoin2") else "rows"
+                kern[op]["per_launch_triples_scanned"] = cw[0] / cl
+                kern[op][f"per_launch_{unit}_relaxed"] = cw[1] / cl
+                kern[op][f"per_launch_{unit}_written"] = cw[2] / cl
+        return per_kernel, kern
+    per_kernel, kern = per_kernel_of(pstats)
     name = max(per_kernel, key=lambda x: per_kernel[x][1])
-    launches, secs, byts, ops = per_kernel[name]
+    timed, _ = per_kernel_of(tstats)
+    launches, secs, byts, ops = timed.get(name, per_kernel[name])
     ach = byts / secs / 1e9 if secs > 0 else 0.0
     traffic = traffic_record(name, workload)
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic, "kernel": name, "ops": sorted(ops), "launches": launches,
-            "avg_launch_ms": 1000.0 * secs / max(1, launches), "alg_bytes_per_launch": byts / max(1, launches)}
+            "avg_launch_ms": 1000.0 * secs / max(1, launches), "alg_bytes_per_launch": byts / max(1, launches),
+            "timing": "HIP events around this kernel's launches over the timed steps"}
     tot_s = sum(v[1] for v in per_kernel.values())
     tot_b = sum(v[2] for v in per_kernel.values())
     uncounted = sorted(k for k, v in per_kernel.items() if v[2] == 0)
     roof["all_kernels"] = {"kernel_s": tot_s, "alg_GB": tot_b / 1e9, "alg_GBps": tot_b / tot_s / 1e9 if tot_s else 0,
                            "frac": tot_b / tot_s / 1e9 / HBM_PEAK_GBS if tot_s else 0,
-                           "kernels_without_byte_count": uncounted}
+                           "kernels_without_byte_count": uncounted,
+                           "timing": "one untimed solve, every launch event-timed"}
     return roof, kern
 
 
@@ -550,9 +556,9 @@ def main():
         cc.count(dg, q, seed0 + 1000 + i, trials)
     times, results = [], []
     prof = not a.no_profile
-    # timed steps: per-launch HIP events on the library's stream (no counters)
+    # timed steps: HIP events on the library's stream around the EdgeJoin launches (no counters)
     cc.profile_take()
-    cc.profile_enable(1 if prof else 0)
+    cc.profile_enable(3 if prof else 0)  # events around the EdgeJoin launches only
     t_all = time.perf_counter()
     for i in range(a.steps):
         t1 = time.perf_counter()
@@ -585,12 +591,17 @@ def main():
     }
     if prof:
         # untimed: the first step's colouring again, with the kernels' byte counters
+        # untimed: one solve with every launch event-timed (the split over kernels)
+        cc.profile_enable(1)
+        cc.count(dg, q, seed0, trials)
+        cc.profile_enable(0)
+        pstats = cc.profile_take()
         cc.profile_enable(2)
         c2 = cc.count(dg, q, seed0, trials)
         cc.profile_enable(0)
         cstats = cc.profile_take()
         assert (int(c2[0][0]), int(c2[1][0])) == results[0], "counting pass disagrees with the timed step"
-        out["roofline"], out["kernels"] = roofline(tstats, cstats, a.workload)
+        out["roofline"], out["kernels"] = roofline(tstats, pstats, cstats, a.workload)
         # the rate of a plain streaming copy on this device: what an HBM-bound kernel can reach
         out["roofline"]["copy_probe_GBps"] = cc.probe_copy(1 << 30, 10)
     if a.batch_trials > 0:

@@ -332,7 +332,8 @@ cc_status cc_server_destroy(cc_server s);
  *   leaf join: computed on the host from the CSR and the table sizes.
  * The one-workgroup-per-source tier and the merges into non-root tables
  * report no bytes.  The counters slow the kernels down: time with level 1.
- * Level 0 turns both off.
+ * Level 3: events around the EdgeJoin launches only (the least timing overhead
+ * for the dominant kernel's launch durations).  Level 0 turns all off.
  */
 typedef struct {
   char name[32];

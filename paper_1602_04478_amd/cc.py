@@ -356,7 +356,7 @@ def probe_copy(nbytes: int, reps: int = 10) -> float:
 
 def profile_enable(level: int = 1):
     """0: off; 1: per-launch HIP-event timing; 2: timing and the kernels'
-    algorithmic-byte counters."""
+    algorithmic-byte counters; 3: event timing of the EdgeJoin launches only."""
     _check(lib().cc_profile_enable(int(level)))
 
 

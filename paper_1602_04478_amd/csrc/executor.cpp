@@ -288,7 +288,7 @@ struct ProfStat {
   uint64_t work[3] = {0, 0, 0};
 };
 std::mutex g_prof_mu;
-int g_prof_on = 0;  // 1: per-launch event timing; 2: also the kernels' work counters
+int g_prof_on = 0;  // 1: per-launch event timing; 2: also the kernels' work counters; 3: events around EdgeJoins only
 std::map<std::string, ProfStat> g_prof;
 
 // Records of the launches of one call (events are resolved at its end).
@@ -323,7 +323,8 @@ static bool by_op() {
 }
 
 struct Profiler {
-  bool on = false, counting = false;
+  bool on = false, counting = false, ej_only = false;
+  bool skipped = false;  // the current launch is not timed (level 3, not an EdgeJoin)
   hipStream_t st;
   struct Rec {
     std::string name;
@@ -341,12 +342,15 @@ struct Profiler {
     if (!allowed) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     on = g_prof_on >= 1;
-    counting = g_prof_on >= 2;
+    counting = g_prof_on == 2;
+    ej_only = g_prof_on == 3;
     if (counting) ctrmem.alloc(sizeof(uint64_t) * 3 * PROF_LANES * kMaxCtr);
   }
   // returns a zeroed counter triple for an EdgeJoin launch (or null)
   uint64_t *begin(const char *name, bool counters, double per_scan, double per_active, double per_entry) {
     if (!on) return nullptr;
+    skipped = ej_only && strncmp(name, "edgejoin", 8) != 0;
+    if (skipped) return nullptr;
     Rec r;
     r.name = name;
     r.ctr = -1;
@@ -368,6 +372,10 @@ struct Profiler {
   }
   // forget the current record (nothing was launched for it)
   void drop() {
+    if (skipped) {
+      skipped = false;
+      return;
+    }
     if (!on || recs.empty()) return;
     give_event(recs.back().a);
     give_event(recs.back().b);
@@ -376,14 +384,18 @@ struct Profiler {
   }
   // the current record's operation name (a launch that turned out to be another kind)
   void rename(const std::string &nm) {
-    if (on && !recs.empty()) recs.back().name = nm;
+    if (on && !skipped && !recs.empty()) recs.back().name = nm;
   }
   // algorithmic bytes of the current record computed on the host
   void add_fixed(double bytes) {
-    if (on && !recs.empty()) recs.back().fixed += bytes;
+    if (on && !skipped && !recs.empty()) recs.back().fixed += bytes;
   }
   void end() {
     if (!on) return;
+    if (skipped) {
+      skipped = false;
+      return;
+    }
     HIP_CHECK(hipEventRecord(recs.back().b, st));
   }
   void finish() {
@@ -419,7 +431,7 @@ struct Profiler {
 
 void profile_enable(int level) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_on = level < 0 ? 0 : level > 2 ? 2 : level;
+  g_prof_on = level < 0 ? 0 : level > 3 ? 3 : level;
 }
 
 std::vector<KernelProfile> profile_read() {
