@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--uneven-n", type=int, default=20_000)
     ap.add_argument("--uneven-trials", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-graphs", type=int, default=4, help="resident graphs of the serving pool")
+    ap.add_argument("--serve-max-edges", type=float, default=1e6, help="edges of the largest pool graph (smallest 1e5)")
+    ap.add_argument("--serve-max-colourings", type=int, default=8, help="colourings per request: 1 .. this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
@@ -311,32 +314,40 @@ def run_uneven(a):
 
 
 def run_serve(a):
-    """Serving: a pool of resident Chung-Lu graphs (m ~ 1e5 .. 1e6, exponent
-    uniform in [2.0, 2.5], seed 5); --serve-requests requests (graph uniform,
-    a generated query of 4-9 nodes, 1-8 colourings) arriving as a Poisson
-    stream at 0.8 x the measured one-at-a-time capacity; latency = completion
-    - arrival."""
+    """Serving: a pool of --serve-graphs resident Chung-Lu graphs (mean degree
+    16, edges log-spaced from 1e5 to --serve-max-edges, exponent uniform in
+    [2.0, 2.5], seed 5); --serve-requests requests (graph uniform, a generated
+    query of 4-9 nodes, 1 .. --serve-max-colourings colourings) arriving as a
+    Poisson stream at 0.8 x the measured one-at-a-time capacity; latency =
+    completion - arrival.  Afterwards up to 16 distinct (graph, query) pairs
+    are solved again alone (plain calls): their counts must equal the served
+    ones."""
     from cc_inputs import graphs, queries as Q
     from paper_1602_04478_amd import cc
     rng = np.random.default_rng(5)
     pool = []
-    for i in range(4):
-        n = int(1e5 * 10 ** (i / 3) / 8)
-        pool.append(graphs.chung_lu(n, 16.0, float(rng.uniform(2.0, 2.5)), None, seed=50 + i))
+    G = a.serve_graphs
+    for i in range(G):
+        m = 1e5 * (a.serve_max_edges / 1e5) ** (i / max(1, G - 1))
+        pool.append(graphs.chung_lu(int(m / 8), 16.0, float(rng.uniform(2.0, 2.5)), None, seed=50 + i))
+        print(f"[bench] serve graph {i}: n={pool[-1].n} m={pool[-1].m}", file=sys.stderr, flush=True)
     dgs = [cc.Graph.from_csr(g) for g in pool]
     qlist = [cc.Query(k, E) for k, E, fam in Q.random_queries(505, 16, 4, 9)]
     reqs = [(int(rng.integers(0, len(pool))), int(rng.integers(0, len(qlist))), int(rng.integers(0, 2**40)),
-             int(rng.integers(1, 9))) for _ in range(a.serve_requests)]
+             int(rng.integers(1, a.serve_max_colourings + 1))) for _ in range(a.serve_requests)]
     # capacity: the first 8 requests one at a time
     t0 = time.perf_counter()
-    for gi, qi, sd, tr in reqs[:8]:
+    for j, (gi, qi, sd, tr) in enumerate(reqs[:8]):
         cc.count(dgs[gi], qlist[qi], sd, tr)
+        print(f"[bench] serve capacity: request {j} (graph {gi}, {tr} colourings) done at "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     svc = (time.perf_counter() - t0) / 8
+    print(f"[bench] serve: {1000 * svc:.0f} ms per request one at a time", file=sys.stderr, flush=True)
     lam = 0.8 / svc
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
     srv = cc.Server(0, max_inflight=4)
     ids = [srv.add_graph(dg) for dg in dgs]
-    pending, lat, done_edges = {}, [], 0
+    pending, lat, done_edges, served, failed = {}, [], 0, {}, []
     t0 = time.perf_counter()
     i = 0
     while i < len(reqs) or pending:
@@ -346,24 +357,43 @@ def run_serve(a):
             pending[srv.submit(ids[gi], qlist[qi], sd, tr)] = i
             i += 1
         for tk, ri in list(pending.items()):
-            r = srv.poll(tk, reqs[ri][3])
+            try:
+                r = srv.poll(tk, reqs[ri][3])
+            except cc.CCError as e:  # the request failed (reported, not retried)
+                failed.append((ri, str(e)))
+                del pending[tk]
+                continue
             if r is not None:
                 lat.append(r[3])
+                served[ri] = [int(x) for x in r[0]]
                 done_edges += reqs[ri][3] * pool[reqs[ri][0]].m
                 del pending[tk]
+                print(f"[bench] serve: {len(lat)} of {len(reqs)} done at {now:.1f} s", file=sys.stderr, flush=True)
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
     srv.close()
+    # alone == served on up to 16 distinct (graph, query) pairs of the smaller half of the pool
+    seen, checked, equal = set(), 0, 0
+    for ri, (gi, qi, sd, tr) in enumerate(reqs):
+        if (gi, qi) in seen or checked >= 16 or gi >= max(1, G // 2) or ri not in served:
+            continue
+        seen.add((gi, qi))
+        alone = [int(x) for x in cc.count(dgs[gi], qlist[qi], sd, tr)[0]]
+        checked += 1
+        equal += alone == served[ri]
+        print(f"[bench] serve check {checked}: alone == served {alone == served[ri]}", file=sys.stderr, flush=True)
     lat = np.array(lat)
     out = {"metric": "colourings*data-edges/sec (exact uint64 colourful counts), served",
            "value": done_edges / wall, "unit": "colourings*edges/s", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": 1000 * wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u64", "data": "synthetic",
-           "config": {"workload": f"serving: {len(reqs)} requests, Poisson arrivals at {lam:.1f}/s "
+           "config": {"workload": f"serving: {len(reqs)} requests, Poisson arrivals at {lam:.2f}/s "
                                   f"(0.8 x one-at-a-time capacity), pool of {len(pool)} graphs "
-                                  f"(m = {', '.join(str(g.m) for g in pool)}), queries of 4-9 nodes, 1-8 colourings"},
+                                  f"(m = {', '.join(str(g.m) for g in pool)}), queries of 4-9 nodes, "
+                                  f"1-{a.serve_max_colourings} colourings"},
            "p50_ms": 1000 * float(np.percentile(lat, 50)), "p99_ms": 1000 * float(np.percentile(lat, 99)),
-           "requests_per_s": len(reqs) / wall, "one_at_a_time_ms": 1000 * svc}
+           "requests_per_s": len(reqs) / wall, "one_at_a_time_ms": 1000 * svc,
+           "alone_equals_served": f"{equal}/{checked}", "failed_requests": failed}
     print(json.dumps(out))
 
 

@@ -2691,6 +2691,9 @@ static bool njmaps_build(int dev, int k) {  // ejm_mu held
           if (S == 0) break;
         }
       }
+      // whole 32-bit words: kernels copy the map into LDS word by word, and the
+      // 16-bit index part ends mid-word when (k - 1) * C * ns is odd
+      h.resize((h.size() + 3) & ~(size_t)3, 0);
       uint32_t *d = (uint32_t *)table_pool_alloc(h.size());
       if (!d) return false;
       if (!upload_sync(d, h.data(), h.size())) return false;

@@ -9,6 +9,7 @@
 // on what else is running.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -165,7 +166,9 @@ cc_status cc_server_submit(cc_server s, int32_t graph_id, cc_query q, uint64_t s
   r.seed = seed;
   r.trials = trials;
   cc::ExecOptions o;
-  r.bytes = cc::footprint(*s->graphs[graph_id], q->plan, trials, o);
+  // a request never claims more than the whole budget: one larger than it
+  // runs alone, with its trial groups and source groups sized to the budget
+  r.bytes = std::min<uint64_t>(cc::footprint(*s->graphs[graph_id], q->plan, trials, o), s->budget);
   r.t_submit = Clock::now();
   s->reqs[r.ticket] = std::move(r);
   s->queue.push_back(s->next_ticket - 1);

@@ -15,6 +15,9 @@ colouring contract, trial t of seed s):
   c4_scaled    Chung-Lu n = 1000, mean 8, exponent 2.1, structural cutoff,
                seed 4; the 20 generated queries of query seed 204 (4-10
                nodes), query i with colourings of seed 204 + i, 16 each.
+  k8_cycle_child  Chung-Lu n = 12500, mean 16, exponent 2.4025014618726903,
+               structural cutoff, seed 50; a 5-cycle and a 4-cycle sharing a
+               node (k = 8); colourings 1098605756710/0 and /1.
   c2_sources   the full-size C2 graph (Chung-Lu n = 1e6, seed 2), 6-cycle +
                pendant, colouring 102/0: the share of sampled root sources
                (matches whose highest vertex in the (degree, id) order is the
@@ -102,6 +105,20 @@ def case_c4_scaled():
     return {"queries": out}
 
 
+def k8_cycle_child_graph():
+    return graphs.chung_lu(12500, 16.0, 2.4025014618726903, None, seed=50)
+
+
+K8_CYCLE_CHILD = (8, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (0, 5), (5, 6), (6, 7), (7, 0)])
+
+
+def case_k8_cycle_child():
+    g = k8_cycle_child_graph()
+    k, E = K8_CYCLE_CHILD
+    seed = 1098605756710
+    return {"seed": seed, "counts": [str(O.db(g, k, E, O.colours(g.n, k, seed, t))) for t in range(2)]}
+
+
 def case_c2_sources():
     g = graphs.workload_graph("cl1m")
     k, E = Q.cycle_pendant(6)
@@ -115,7 +132,7 @@ def case_c2_sources():
 
 
 CASES = {"c2_scaled": case_c2_scaled, "c3_scaled": case_c3_scaled, "c4_scaled": case_c4_scaled,
-         "c2_sources": case_c2_sources}
+         "c2_sources": case_c2_sources, "k8_cycle_child": case_k8_cycle_child}
 
 
 def main(names):

@@ -149,6 +149,34 @@ def _star_forest(hubs, leaves):
     return graphs.from_edges(n, np.array(e, dtype=np.int64))
 
 
+K8_CYCLE_CHILD = (8, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (0, 5), (5, 6), (6, 7), (7, 0)])
+
+
+@pytest.mark.parametrize("mode", ["auto", "dense", "sparse"])
+def test_k8_cycle_child_every_tree(mode, monkeypatch):
+    """A 5-cycle and a 4-cycle sharing a node (k = 8) on a 12500-vertex
+    Chung-Lu graph: every tree, two colourings per call and one, repeated
+    (equal every time).  NodeJoin terms read split maps whose 16-bit index
+    part ends mid-word when (k - 1) * C * ns is odd; a map cut to whole words
+    without that last entry gave counts that changed from run to run."""
+    env = {"auto": {}, "dense": {"CC_DENSE": "all"}, "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"}}[mode]
+    for key, val in env.items():
+        monkeypatch.setenv(key, val)
+    gold = _gold("k8_cycle_child")
+    want = [int(x) for x in gold["counts"]]
+    g = graphs.chung_lu(12500, 16.0, 2.4025014618726903, None, seed=50)
+    dg = cc.Graph.from_csr(g)
+    k, E = K8_CYCLE_CHILD
+    for tree in range(cc.Query(k, E).tree_info()["num_trees"]):
+        q = cc.Query(k, E, tree=tree)
+        print(f"[scale] k8 cycle child, tree {tree}, mode {mode}", flush=True)
+        for _ in range(2):
+            counts, ovf, exact, est = cc.count(dg, q, gold["seed"], 2)
+            assert [int(x) for x in exact] == want and not ovf.any(), (tree, mode, exact, want)
+        for t in range(2):
+            assert int(cc.count(dg, q, gold["seed"] + t, 1)[2][0]) == want[t], (tree, mode, t)
+
+
 def test_sum_overflow_reported_exactly():
     """2000 hubs of 500 leaves, 8-node star: every hub's count fits in 64
     bits, their sum does not."""
