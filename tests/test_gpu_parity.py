@@ -221,6 +221,27 @@ def test_path_splitting_plans(small_graphs, name, mode, monkeypatch):
             assert not ovf[t] and exact[t] == want, (name, gi, t, exact[t], want)
 
 
+@pytest.mark.parametrize("qseed,count,kmax", [(505, 16, 9), (204, 20, 10)])
+def test_maps_equal_subset_walk(qseed, count, kmax, monkeypatch):
+    """The EdgeJoin slot maps and NodeJoin split maps (tables built on the host
+    once per k) give the counts of the slot arithmetic they replace, on a
+    3000-vertex power-law graph for generated queries of 4-10 nodes, with two
+    colourings per call and with one."""
+    g = graphs.chung_lu(3000, 16.0, 2.3, None, seed=7)
+    dg = cc.Graph.from_csr(g)
+    for i, (k, E, fam) in enumerate(Q.random_queries(qseed, count, 4, kmax)):
+        q = cc.Query(k, E)
+        print(f"[parity] maps vs walk: query {i} ({fam}, k={k})", flush=True)
+        with_maps = cc.count(dg, q, 900 + i, 2)[2]
+        one = [cc.count(dg, q, 900 + i + t, 1)[2][0] for t in range(2)]
+        monkeypatch.setenv("CC_NJMAP", "0")
+        monkeypatch.setenv("CC_EJMAP", "0")
+        walk = cc.count(dg, q, 900 + i, 2)[2]
+        monkeypatch.delenv("CC_NJMAP")
+        monkeypatch.delenv("CC_EJMAP")
+        assert with_maps == walk == one, (qseed, i, k, fam, with_maps, walk, one)
+
+
 def test_every_tree_same_count(small_graphs):
     """Every decomposition tree of a query gives the same count (the choice
     of tree is a cost knob only)."""
