@@ -292,8 +292,9 @@ cc_status cc_last_solve_stats(cc_solve_stats *out);
  * are admitted while their device footprint fits the budget and fewer than
  * `max_inflight` are running; admitted requests run concurrently on a pool of
  * streams (continuous batching: a request arriving while others run starts as
- * soon as a stream slot and memory are free).  Results are identical to
- * cc_count on the same arguments.
+ * soon as a stream slot and memory are free).  A request whose footprint
+ * exceeds the budget runs alone within the budget (smaller trial and source
+ * groups).  Results are identical to cc_count on the same arguments.
  */
 cc_status cc_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, cc_server *out);
 /* Register a resident graph; the server does not take ownership. */
