@@ -251,19 +251,23 @@ __global__ void k_cmp_emit(uint64_t *mb, int64_t nv, const uint32_t *boff, int64
   for (int i = 0; i < CPER; i++) {
     const int64_t v = lo + (int64_t)i * BLK + threadIdx.x;
     const uint64_t mm = v < nv ? mb[2 * v] : 0;
-    uint32_t tot, vtot;
-    const uint32_t id0 = run + block_scan((uint32_t)__popcll(mm), s, tot);
-    const uint32_t vid = vrun + block_scan(mm != 0 ? 1u : 0u, s, vtot);
+    // one scan of both counts: entries in the high 16 bits (at most 256 * 64
+    // per step), marked vertices in the low 16 bits (at most 256)
+    uint32_t tot;
+    const uint32_t pk = block_scan(((uint32_t)__popcll(mm) << 16) | (mm != 0 ? 1u : 0u), s, tot);
+    const uint32_t id0 = run + (pk >> 16), vid = vrun + (pk & 0xffffu);
     if (v < nv) {
-      mb[2 * v + 1] = id0;
       uint32_t id = id0;
-      for (uint64_t r = mm; r; r &= r - 1) list[id++] = v * 64 + __builtin_ctzll(r);
-      if (mm) vlist[vid] = (int32_t)v;
+      if (mm) {  // the base of an unmarked vertex is never read (its marks are zero)
+        mb[2 * v + 1] = id0;
+        for (uint64_t r = mm; r; r &= r - 1) list[id++] = v * 64 + __builtin_ctzll(r);
+        vlist[vid] = (int32_t)v;
+      }
       prd += 8;
-      pwr += 8 + 8 * (uint64_t)__popcll(mm) + (mm ? 4 : 0);
+      pwr += mm ? 8 + 8 * (uint64_t)__popcll(mm) + 4 : 0;
     }
-    run += tot;
-    vrun += vtot;
+    run += tot >> 16;
+    vrun += tot & 0xffffu;
   }
   prof_flush(prof, prd, pwr, 0);
 }
