@@ -330,9 +330,11 @@ cc_status cc_server_destroy(cc_server s);
  *   NodeJoin, AXPY chains, path init, root merge, level builds: the bytes of
  *             the rows they read and write (8 B per slot, 8-16 B per vertex
  *             word), counted by the kernels themselves;
- *   leaf join: computed on the host from the CSR and the table sizes.
- * The one-workgroup-per-source tier and the merges into non-root tables
- * report no bytes.  The counters slow the kernels down: time with level 1.
+ *   leaf join: computed on the host from the CSR and the table sizes;
+ *   one-workgroup-per-source tier: the same per-operation bytes for the rows
+ *             it keeps in its scratch, plus 4 B per neighbour scanned while
+ *             it builds its key lists.
+ * The merges into non-root tables report no bytes.  The counters slow the kernels down: time with level 1.
  * Level 3: events around the EdgeJoin launches only (the least timing overhead
  * for the dominant kernel's launch durations).  Level 0 turns all off.
  */

@@ -1607,7 +1607,8 @@ void Solver::run_light(Light &L, bool probe, int Tg, Profiler *prof) {
   L.la.T = Tg;
   L.la.acc = acc_;
   launch_fill_u64((uint64_t *)L.d_ctr.p, 1, st);
-  if (prof) prof->begin(L.large ? "light_large" : "light", false, 0, 0, 0);
+  // the kernel counts its bytes read and written itself (level 2)
+  L.la.prof = prof ? prof->begin(L.large ? "light_large" : "light", true, 1.0, 1.0, 0.0) : nullptr;
   launch_light(L.la, L.grid, L.large, st);
   HIP_CHECK(hipGetLastError());
   if (prof) prof->end();

@@ -230,6 +230,7 @@ struct LightArgs {
   uint8_t *scratch;
   int64_t scratch_per_wg;
   const uint16_t *lut;
+  uint64_t *prof;       // profiling: PROF_LANES (read, written, 0) byte triples, or null
 };
 
 int light_max_depth();

@@ -109,6 +109,10 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
   const int T = A.T, k = A.k;
   const uint32_t Kmask = (1u << k) - 1u;
   uint8_t *base = A.scratch + (int64_t)blockIdx.x * A.scratch_per_wg;
+  // profiling (A.prof set): algorithmic bytes read and written by this
+  // thread, counted as in the grouped kernels (rows of the registers and
+  // tables, 4 B per scanned neighbour)
+  uint64_t prd = 0, pwr = 0;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -141,9 +145,11 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
       __syncthreads();
       for (int i = k0 + threadIdx.x; i < k1; i += BLK) {
         int64_t v = s_k[i];
+        if (A.prof) prd += 16;
         for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
           int32_t w = g.col[e];
           if (w >= ub) break;
+          if (A.prof) prd += 4;
           int pos = atomicAdd(&s_n, 1);
           if (pos < EMAX) s_c[pos] = w;
         }
@@ -294,6 +300,10 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
           }
           dv[(int64_t)xi * T * C + t * C + c] = acc;
           if (of) ofm |= 1ull << t;
+          if (A.prof) {
+            pwr += 8;
+            if (c == 0) prd += 4 + 2 + 8 * ((nt.val ? nt.C : 0) + (et.val ? et.C : 0));
+          }
         }
       } else if (op.kind == OP_NJ) {
         const int d = A.reg_depth[op.a];
@@ -328,6 +338,10 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
           }
           dv[((int64_t)i * T + t) * C + c] = acc;
           if (of) ofm |= 1ull << t;
+          if (A.prof) {
+            pwr += 8;
+            if (c == 0 && cu != cv) prd += 8 * (uint64_t)(Ca + nt.C);
+          }
         }
       } else if (op.kind == OP_EJ) {
         const int j = A.reg_depth[op.a];
@@ -377,6 +391,15 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
           }
           dv[((int64_t)wi * T + t) * C + c] = acc;
           if (of) ofm |= 1ull << t;
+          if (A.prof) {
+            pwr += 8;
+            if (c == 0)  // per (output key, trial): the scanned matches and the input rows they relax
+              for (int m = offs[wi]; m < offs[wi + 1]; m++) {
+                prd += 4;
+                const int cv = A.colr[(int64_t)t * g.n + s_k[kk0 + mp[m]]];
+                if (cu != cw && cv != cu && cv != cw) prd += 8 * (uint64_t)(Ca + (et.val ? et.C : 0));
+              }
+          }
         }
       } else if (op.kind == OP_AXPY) {
         const int d = A.reg_depth[op.a];
@@ -391,6 +414,10 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
           add_ck(y, x, of);
           dv[it] = y;
           if (of) ofm |= 1ull << ((it / C) % T);
+          if (A.prof) {
+            prd += op.first ? 8 : 16;
+            pwr += 8;
+          }
         }
       } else if (op.kind == OP_MROOT) {
         const int da = A.reg_depth[op.a], db = A.reg_depth[op.b];
@@ -408,6 +435,7 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
           if (pb < 0) continue;
           const int cu = A.colr[(int64_t)t * g.n + u], cv = A.colr[(int64_t)t * g.n + v];
           if (cu == cv) continue;
+          if (A.prof) prd += 16;
           const uint32_t R1 = spread2(unrank(A.lut, sa - 2, c), cu, cv);
           const uint32_t R2 = Kmask & ~R1 & ~(1u << cu) & ~(1u << cv);
           const uint64_t y = bv[((int64_t)pb * T + t) * Cb + s_rank[squeeze2(R2, cu, cv)]];
@@ -586,6 +614,17 @@ __global__ __launch_bounds__(BLK) void k_light(LightArgs A) {
         atomic_add128(&A.acc.sum[2 * t], lo, hi);
         if (A.acc.per_src) atomic_add128(&A.acc.per_src[2 * (u * T + t)], lo, hi);
       }
+    }
+  }
+  if (A.prof) {
+    for (int o = 32; o > 0; o >>= 1) {
+      prd += __shfl_xor(prd, o);
+      pwr += __shfl_xor(pwr, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      uint64_t *pc = A.prof + 3 * ((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % PROF_LANES);
+      if (prd) atomicAdd((unsigned long long *)&pc[0], (unsigned long long)prd);
+      if (pwr) atomicAdd((unsigned long long *)&pc[1], (unsigned long long)pwr);
     }
   }
 }

@@ -242,6 +242,31 @@ def test_maps_equal_subset_walk(qseed, count, kmax, monkeypatch):
         assert with_maps == walk == one, (qseed, i, k, fam, with_maps, walk, one)
 
 
+def test_profiling_leaves_counts_and_reports_bytes():
+    """Event timing (levels 1 and 3) and the kernels' byte counters (level 2)
+    change no count, and every operation but the merges into non-root tables
+    reports algorithmic bytes, the one-workgroup tier included."""
+    g = graphs.chung_lu(3000, 16.0, 2.3, None, seed=7)
+    dg = cc.Graph.from_csr(g)
+    q = cc.Query(*Q.cycle_pendant(6))
+    base = cc.count(dg, q, 77, 2)[2]
+    cc.profile_take()
+    for level in (1, 2, 3):
+        cc.profile_enable(level)
+        got = cc.count(dg, q, 77, 2)[2]
+        cc.profile_enable(0)
+        stats = cc.profile_take()
+        assert got == base, (level, got, base)
+        assert stats, level
+        if level == 2:
+            assert any(name.startswith("light") for name in stats), sorted(stats)
+            for name, (launches, secs, byts, work) in stats.items():
+                if not name.startswith(("merge_u", "merge_v", "merge_edge", "merge_pair")):
+                    assert byts > 0, (name, launches, byts)
+        if level == 3:
+            assert all(name.startswith("edgejoin") for name in stats), sorted(stats)
+
+
 def test_every_tree_same_count(small_graphs):
     """Every decomposition tree of a query gives the same count (the choice
     of tree is a cost knob only)."""
