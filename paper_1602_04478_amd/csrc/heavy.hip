@@ -998,7 +998,8 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
               const uint32_t R2 = Kmask & ~R1 & ~(1u << cu) & ~(1u << cw);
               const uint64_t y = val(op.b, s_rank[squeeze2(R2, cu, cw)]);
               if (!y) continue;
-              uint64_t pl = x * y, ph = __umul64hi(x, y);
+              uint64_t pl, ph;
+    mul_wide(x, y, pl, ph);
               if (op.w != 1) {
                 const uint64_t l2 = pl * op.w, c2 = __umul64hi(pl, op.w);
                 const uint64_t h2 = ph * op.w + c2;
@@ -1535,7 +1536,7 @@ __global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, con
         xq = xp[q];
         prd += 8;
       }
-      if (xq) add_ck(y, mul_ck(tm.w[q], xq, of), of);
+      if (xq) add_ck(y, tm.w[q] == 1 ? xq : mul_ck(tm.w[q], xq, of), of);
     }
     return y;
   };
@@ -1579,11 +1580,12 @@ __global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, con
         for (int q = 0; q < NT; q++) {
           if (!tm.nt[q].val) continue;
           const int Cq = tm.a[q].C;
-          for (int i = lane; i < R * Cq; i += 64) {
-            const int r = i / Cq;
-            if (j0 + r >= nrows) break;
-            const int br = nth_bit(m, j0 + r);
-            if ((mt[q] >> br) & 1ull) stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
+          // row r's source comes from the lane that owns row r (lane r * C)
+          for (int i0 = 0; i0 < R * Cq; i0 += 64) {
+            const int i = i0 + lane, r = min(i / Cq, R - 1);
+            const int br = __shfl(b, r * C);
+            if (i < R * Cq && j0 + r < nrows && ((mt[q] >> br) & 1ull))
+              stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
           }
         }
         wave_lds_sync();
@@ -1701,7 +1703,8 @@ __global__ __launch_bounds__(BLK) void k_mroot(GroupDev grp, int64_t n, const ui
         for (int q = 0; q < 4; q++) {
           const uint64_t x = xs[q], y = ys[q];
           if (!x || !y) continue;
-          uint64_t pl = x * y, ph = __umul64hi(x, y);
+          uint64_t pl, ph;
+    mul_wide(x, y, pl, ph);
           if (w != 1) {
             const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
             const uint64_t h2 = ph * w + c2;
@@ -1799,7 +1802,8 @@ __global__ __launch_bounds__(BLK) void k_mroot_terms(GroupDev grp, int64_t n, co
     if (!x) return;
     const uint64_t y = bb.val[(eb * T + t) * Cb + s_yi[c]];
     if (!y) return;
-    uint64_t pl = x * y, ph = __umul64hi(x, y);
+    uint64_t pl, ph;
+    mul_wide(x, y, pl, ph);
     if (w != 1) {
       const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
       const uint64_t h2 = ph * w + c2;
@@ -1950,10 +1954,11 @@ __global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, con
       } else {
         xq = xp[q];
       }
-      if (xq) add_ck(x, mul_ck(tm.w[q], xq, of), of);
+      if (xq) add_ck(x, tm.w[q] == 1 ? xq : mul_ck(tm.w[q], xq, of), of);
     }
     if (!x) return;
-    uint64_t pl = x * y, ph = __umul64hi(x, y);
+    uint64_t pl, ph;
+    mul_wide(x, y, pl, ph);
     if (w != 1) {
       const uint64_t l2 = pl * w, c2 = __umul64hi(pl, w);
       const uint64_t h2 = ph * w + c2;
@@ -2013,11 +2018,20 @@ __global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, con
         for (int q = 0; q < NT; q++) {
           if (!tm.nt[q].val) continue;
           const int Cq = tm.a[q].C;
-          for (int i = lane; i < R * Cq; i += 64) {
-            const int r = i / Cq;
-            if (j0 + r >= nrows) break;
-            const int br = nth_bit(m, j0 + r);
-            if ((mt[q] >> br) & 1ull) stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
+          if (IPL == 1) {  // row r's source comes from the lane that owns row r (lane r * C)
+            for (int i0 = 0; i0 < R * Cq; i0 += 64) {
+              const int i = i0 + lane, r = min(i / Cq, R - 1);
+              const int br = __shfl(bi[0], r * C);
+              if (i < R * Cq && j0 + r < nrows && ((mt[q] >> br) & 1ull))
+                stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
+            }
+          } else {
+            for (int i = lane; i < R * Cq; i += 64) {
+              const int r = i / Cq;
+              if (j0 + r >= nrows) break;
+              const int br = nth_bit(m, j0 + r);
+              if ((mt[q] >> br) & 1ull) stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
+            }
           }
         }
         wave_lds_sync();

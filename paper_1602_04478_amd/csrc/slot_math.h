@@ -63,10 +63,22 @@ __device__ __forceinline__ void add_ck(uint64_t &acc, uint64_t a, bool &of) {
   of |= s < acc;
   acc = s;
 }
-// a * b (checked)
+// a * b (checked).  Both factors below 2^32 (the common case): one 32 x 32
+// multiply and no overflow is possible; otherwise the high word decides.
 __device__ __forceinline__ uint64_t mul_ck(uint64_t a, uint64_t b, bool &of) {
+  if (((a | b) >> 32) == 0) return (uint64_t)(uint32_t)a * (uint32_t)b;
   of |= __umul64hi(a, b) != 0;
   return a * b;
+}
+// the 128-bit product (lo, hi) of a and b
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+  if (((a | b) >> 32) == 0) {
+    lo = (uint64_t)(uint32_t)a * (uint32_t)b;
+    hi = 0;
+  } else {
+    lo = a * b;
+    hi = __umul64hi(a, b);
+  }
 }
 // global acc += a (checked through the returned old value)
 __device__ __forceinline__ void atomic_add_ck(uint64_t *p, uint64_t a, bool &of) {
