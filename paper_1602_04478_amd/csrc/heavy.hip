@@ -1504,6 +1504,15 @@ __global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, con
       off += (DENSE ? 1 : R) * tm.nt[q].C;
     }
   }
+  // the lane's first staged node-table element (sparse groups stage one row per
+  // entry): its entry of the chunk and slot
+  int nr0[NT], nc0[NT];
+#pragma unroll
+  for (int q = 0; q < NT; q++) {
+    const int Cn = tm.nt[q].val ? tm.nt[q].C : 1;
+    nr0[q] = min(lane / Cn, R - 1);
+    nc0[q] = lane - (lane / Cn) * Cn;
+  }
   const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
   uint64_t prd = 0, pwr = 0;
   bool of = false;
@@ -1582,7 +1591,8 @@ __global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, con
           const int Cq = tm.a[q].C;
           // row r's source comes from the lane that owns row r (lane r * C)
           for (int i0 = 0; i0 < R * Cq; i0 += 64) {
-            const int i = i0 + lane, r = min(i / Cq, R - 1);
+            const int i = i0 + lane;
+            const int r = min(i / Cq, R - 1);
             const int br = __shfl(b, r * C);
             if (i < R * Cq && j0 + r < nrows && ((mt[q] >> br) & 1ull))
               stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
@@ -1622,10 +1632,12 @@ __global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, con
         if (!tm.nt[q].val) continue;
         const int Cq = tm.a[q].C, Cn = tm.nt[q].C;
         for (int i = lane; i < lim * Cq; i += 64) stg[off_a[q] + i] = tm.a[q].val[e0 * Cq + i];
-        for (int i = lane; i < lim * Cn; i += 64) {
-          const int r = i / Cn;
-          const int64_t vr = L.list[e0 + r] >> 6;
-          stg[off_n[q] + i] = tm.nt[q].val[vr * Cn + (i - r * Cn)];
+        // row r's vertex comes from the lane that owns entry r (lane r * C)
+        for (int i0 = 0; i0 < lim * Cn; i0 += 64) {
+          const int i = i0 + lane;
+          const int r = i0 ? min(i / Cn, R - 1) : nr0[q], cc = i0 ? i - (i / Cn) * Cn : nc0[q];
+          const int vr = __shfl((int)v, r * C);
+          if (i < lim * Cn) stg[off_n[q] + i] = tm.nt[q].val[(int64_t)vr * Cn + cc];
         }
       }
       wave_lds_sync();
@@ -1919,6 +1931,15 @@ __global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, con
       off += (DENSE ? 1 : R) * tm.nt[q].C;
     }
   }
+  // the lane's first staged node-table element (sparse groups stage one row per
+  // entry): its entry of the chunk and slot
+  int nr0[NT], nc0[NT];
+#pragma unroll
+  for (int q = 0; q < NT; q++) {
+    const int Cn = tm.nt[q].val ? tm.nt[q].C : 1;
+    nr0[q] = min(lane / Cn, R - 1);
+    nc0[q] = lane - (lane / Cn) * Cn;
+  }
   const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
   const bool same_level = La.mb == Lb.mb;  // sparse: the partner row has the same entry
   uint64_t tlo = 0, thi = 0, prd = 0;
@@ -2020,7 +2041,8 @@ __global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, con
           const int Cq = tm.a[q].C;
           if (IPL == 1) {  // row r's source comes from the lane that owns row r (lane r * C)
             for (int i0 = 0; i0 < R * Cq; i0 += 64) {
-              const int i = i0 + lane, r = min(i / Cq, R - 1);
+              const int i = i0 + lane;
+              const int r = min(i / Cq, R - 1);
               const int br = __shfl(bi[0], r * C);
               if (i < R * Cq && j0 + r < nrows && ((mt[q] >> br) & 1ull))
                 stg[off_a[q] + i] = tm.a[q].val[(v * B + br) * Cq + (i - r * Cq)];
@@ -2077,10 +2099,19 @@ __global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, con
         if (!tm.nt[q].val) continue;
         const int Cq = tm.a[q].C, Cn = tm.nt[q].C;
         for (int i = lane; i < lim * Cq; i += 64) stg[off_a[q] + i] = tm.a[q].val[e0 * Cq + i];
-        for (int i = lane; i < lim * Cn; i += 64) {
-          const int r = i / Cn;
-          const int64_t vr = La.list[e0 + r] >> 6;
-          stg[off_n[q] + i] = tm.nt[q].val[vr * Cn + (i - r * Cn)];
+        if (IPL == 1) {  // row r's vertex comes from the lane that owns entry r (lane r * C)
+          for (int i0 = 0; i0 < lim * Cn; i0 += 64) {
+            const int i = i0 + lane;
+            const int r = i0 ? min(i / Cn, R - 1) : nr0[q], cc = i0 ? i - (i / Cn) * Cn : nc0[q];
+            const int vr = __shfl((int)v[0], r * C);
+            if (i < lim * Cn) stg[off_n[q] + i] = tm.nt[q].val[(int64_t)vr * Cn + cc];
+          }
+        } else {
+          for (int i = lane; i < lim * Cn; i += 64) {
+            const int r = i / Cn;
+            const int64_t vr = La.list[e0 + r] >> 6;
+            stg[off_n[q] + i] = tm.nt[q].val[vr * Cn + (i - r * Cn)];
+          }
         }
       }
       wave_lds_sync();
