@@ -169,7 +169,9 @@ cc_status cc_colors(cc_graph g, int32_t k, uint64_t seed, int32_t trial, uint8_t
 
 /*
  * Count colourful matches of q in g for `trials` colourings drawn by the
- * contract above from `seed` (trial t uses seed + t).
+ * contract above from `seed` (trial t uses seed + t): the colour-coding count
+ * of Section 2, computed over the decomposition tree (Sections 4.1-4.3) with
+ * the degree-based cycle solution (Section 5.1, Eq. (1)), and its estimate.
  *   counts    host, uint64[trials]: exact counts; UINT64_MAX when overflow[t] = 1.
  *   overflow  host, uint8[trials]: 1 if the count is >= 2^64 or a table entry
  *             left 64 bits during the computation (sticky per trial).
@@ -185,7 +187,8 @@ cc_status cc_count(cc_graph g, cc_query q, uint64_t seed, int32_t trials, uint64
                    uint8_t *overflow, cc_u128 *exact, double *estimate, void *stream);
 
 /*
- * As cc_count, with the colourings given: `colors` is host, uint8[trials*n],
+ * As cc_count (Section 2, Sections 4.1-5.2), with the colourings given:
+ * `colors` is host, uint8[trials*n],
  * trial-major, indexed by original vertex id, values in [0, k).
  * `per_source` (host, cc_u128[trials*n] or NULL) receives, for a query whose
  * root block is a cycle, the count of colourful matches whose highest root
@@ -222,7 +225,9 @@ cc_status cc_count_static(cc_graph g, cc_query q, uint64_t seed, int32_t trials,
 /*
  * Batched form: nq queries on one graph, query i with trials[i] colourings
  * from seeds[i] (trial t of query i uses the colouring (seeds[i], t) of the
- * contract, so the counts equal cc_count's).  The colourings of a query are
+ * contract, so the counts equal cc_count's).  The trials are the independent
+ * colourings whose counts the estimate averages (Section 2; the number of
+ * trials sets its precision, Section 8).  The colourings of a query are
  * solved in trial groups that form the batch dimension of every launch; the
  * launch sequence of a trial group is captured once in a hipGraph and
  * replayed for the next groups (use_graphs).  With several queries, up to
