@@ -1185,17 +1185,22 @@ struct AxpyTerms {
 };
 
 // NodeJoin splits from a map.  For output slot c (colour set S of dst, cu and
-// cv squeezed out) the splits are the subsets S_j of S of nt's size: xi[j] is
-// the slot of S minus S_j in a (it does not depend on the colours), yi[j] the
-// slot of S_j in nt's row, where only the position of cu among the k - 1
-// colours other than cv matters (cu' = cu - [cv < cu]).
-__device__ __forceinline__ uint64_t nj_slot_map(const uint64_t *ar, const uint64_t *nr, const uint8_t *xi,
-                                                const uint16_t *yi, int ns, bool &of) {
+// cv squeezed out) the splits are the subsets S_j of S of nt's size; the map
+// word of split j holds the slot of S_j in nt's row in its low 16 bits (only
+// the position of cu among the k - 1 colours other than cv matters: cu' = cu -
+// [cv < cu]) and the slot of S minus S_j in a in its high 16 bits (it does not
+// depend on the colours).  Words of (cu', c) start at (cu' * C + c) * ns.
+__device__ __forceinline__ const uint32_t *split_words(const uint32_t *jm, int cup, int C, int c, int ns) {
+  return jm + (cup * C + c) * ns;
+}
+__device__ __forceinline__ uint64_t nj_slot_map(const uint64_t *ar, const uint64_t *nr, const uint32_t *sp, int ns,
+                                                bool &of) {
   uint64_t acc = 0;
   for (int j = 0; j < ns; j++) {
-    const uint64_t y = nr[yi[j]];
+    const uint32_t w = sp[j];
+    const uint64_t y = nr[w & 0xffffu];
     if (!y) continue;
-    const uint64_t x = ar[xi[j]];
+    const uint64_t x = ar[w >> 16];
     if (x) add_ck(acc, mul_ck(x, y, of), of);
   }
   return acc;
@@ -1273,9 +1278,8 @@ __global__ __launch_bounds__(BLK) void k_axpyn(GroupDev grp, int64_t n, const ui
           if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
           if (tm.jmw[q]) {
             const int ns = tm.jns[q];
-            const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
-            const uint16_t *yi = (const uint16_t *)(jmap_at(tm, s_jm, q) + ((C * ns + 3) >> 2)) + ((cu - (cv < cu)) * C + c) * ns;
-            x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi, yi,
+            const uint32_t *sp = split_words(jmap_at(tm, s_jm, q), cu - (cv < cu), C, c, ns);
+            x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, sp,
                             ns, of);
           } else {
             x = nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of);
@@ -1442,11 +1446,9 @@ __global__ __launch_bounds__(BLK) void k_axpyn_dense(GroupDev grp, int64_t n, co
             if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
             if (JM || tm.jmw[q]) {
               const int ns = tm.jns[q];
-              const uint8_t *xi = (const uint8_t *)jmap_at(tm, s_jm, q) + c * ns;
-              const uint16_t *yi =
-                  (const uint16_t *)(jmap_at(tm, s_jm, q) + ((C * ns + 3) >> 2)) + ((cu - (cv < cu)) * C + c) * ns;
-              x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi,
-                              yi, ns, of);
+              const uint32_t *sp = split_words(jmap_at(tm, s_jm, q), cu - (cv < cu), C, c, ns);
+              x = nj_slot_map(tm.a[q].val + (row * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, sp,
+                              ns, of);
             } else {
               x = nj_slot(tm.a[q], tm.nt[q], row, v, t, T, cu, cv, s_uo[c], s_rank, of);
             }
@@ -1531,14 +1533,14 @@ __global__ __launch_bounds__(BLK) void k_axpyn_rows(GroupDev grp, int64_t n, con
         if (c == 0) prd += 8 * (uint64_t)(tm.a[q].C + tm.nt[q].C);
         const int ns = tm.jns[q];
         const uint32_t *jm = jmap_at(tm, s_jm, q);
-        const uint8_t *xi = (const uint8_t *)jm + c * ns;
-        const uint16_t *yi = (const uint16_t *)(jm + ((C * ns + 3) >> 2)) + (cup * C + c) * ns;
+        const uint32_t *sp = split_words(jm, cup, C, c, ns);
         const uint64_t *ar = stg + off_a[q] + jr * tm.a[q].C;
         const uint64_t *nr = stg + off_n[q] + (DENSE ? 0 : jr * tm.nt[q].C);
         for (int j = 0; j < ns; j++) {
-          const uint64_t z = nr[yi[j]];
+          const uint32_t w = sp[j];
+          const uint64_t z = nr[w & 0xffffu];
           if (!z) continue;
-          const uint64_t xa = ar[xi[j]];
+          const uint64_t xa = ar[w >> 16];
           if (xa) add_ck(xq, mul_ck(xa, z, of), of);
         }
       } else {
@@ -1767,10 +1769,8 @@ __device__ __forceinline__ uint64_t chain_slot(const AxpyTerms &tm, const uint32
       if (!below) continue;
       const int ns = tm.jns[q];
       const uint32_t *jm = jmap_at(tm, s_jm, q);
-      const uint8_t *xi = (const uint8_t *)jm + c * ns;
-      const uint16_t *yi = (const uint16_t *)(jm + ((C * ns + 3) >> 2)) + (cup * C + c) * ns;
-      xq = nj_slot_map(tm.a[q].val + (e * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C, xi, yi, ns,
-                       of);
+      xq = nj_slot_map(tm.a[q].val + (e * T + t) * tm.a[q].C, tm.nt[q].val + (v * T + t) * tm.nt[q].C,
+                       split_words(jm, cup, C, c, ns), ns, of);
     } else {
       xq = tm.a[q].val[(e * T + t) * C + c];
     }
@@ -1962,14 +1962,14 @@ __global__ __launch_bounds__(BLK) void k_mroot_rows(GroupDev grp, int64_t n, con
         if (!below) continue;
         const int ns = tm.jns[q];
         const uint32_t *jm = jmap_at(tm, s_jm, q);
-        const uint8_t *xi = (const uint8_t *)jm + ci * ns;
-        const uint16_t *yi = (const uint16_t *)(jm + ((C * ns + 3) >> 2)) + (cup * C + ci) * ns;
+        const uint32_t *sp = split_words(jm, cup, C, ci, ns);
         const uint64_t *ar = stg + off_a[q] + jri * tm.a[q].C;
         const uint64_t *nr = stg + off_n[q] + (DENSE ? 0 : jri * tm.nt[q].C);
         for (int j = 0; j < ns; j++) {
-          const uint64_t z = nr[yi[j]];
+          const uint32_t w = sp[j];
+          const uint64_t z = nr[w & 0xffffu];
           if (!z) continue;
-          const uint64_t xa = ar[xi[j]];
+          const uint64_t xa = ar[w >> 16];
           if (xa) add_ck(xq, mul_ck(xa, z, of), of);
         }
       } else {
@@ -2719,35 +2719,31 @@ static bool njmaps_build(int dev, int k) {  // ejm_mu held
   for (int ro = 1; ro <= k - 2; ro++)
     for (int rA = 1; rA <= ro; rA++) {
       const int C = host_binom(k - 2, ro), ns = host_binom(ro, rA);
-      const size_t xb = ((size_t)C * ns + 3) & ~(size_t)3, yb = (size_t)(k - 1) * C * ns * 2;
-      if (xb + yb > NJMAP_MAX || host_binom(k - 2, ro - rA) > 255 || host_binom(k - 1, rA) > 65535) continue;
+      const size_t bytes = (size_t)(k - 1) * C * ns * 4;  // one 32-bit word per (cu', c, split)
+      if (bytes > NJMAP_MAX || host_binom(k - 2, ro - rA) > 65535 || host_binom(k - 1, rA) > 65535) continue;
       std::vector<uint32_t> uo(C);
       for (uint32_t m = 0; m < (1u << (k - 2)); m++)
         if (__builtin_popcount(m) == ro) uo[host_rank(m)] = m;
-      std::vector<uint8_t> h(xb + yb, 0);
-      uint16_t *yi = (uint16_t *)(h.data() + xb);
+      std::vector<uint32_t> h((size_t)(k - 1) * C * ns, 0);
       for (int c = 0; c < C; c++) {
         int j = 0;
         for (uint32_t S = uo[c];; S = (S - 1) & uo[c]) {  // subsets of uo[c] of size rA, in a fixed order
           if (__builtin_popcount(S) == rA) {
-            h[(size_t)c * ns + j] = (uint8_t)host_rank(uo[c] & ~S);
+            const uint32_t xi = (uint32_t)host_rank(uo[c] & ~S);  // the input row's slot
             for (int cu = 0; cu < k - 1; cu++) {
               const uint32_t Sp = (S & ((1u << cu) - 1u)) | ((S >> cu) << (cu + 1));  // zero inserted at cu
-              yi[((size_t)cu * C + c) * ns + j] = (uint16_t)host_rank(Sp);
+              h[((size_t)cu * C + c) * ns + j] = (uint32_t)host_rank(Sp) | (xi << 16);
             }
             j++;
           }
           if (S == 0) break;
         }
       }
-      // whole 32-bit words: kernels copy the map into LDS word by word, and the
-      // 16-bit index part ends mid-word when (k - 1) * C * ns is odd
-      h.resize((h.size() + 3) & ~(size_t)3, 0);
-      uint32_t *d = (uint32_t *)table_pool_alloc(h.size());
+      uint32_t *d = (uint32_t *)table_pool_alloc(bytes);
       if (!d) return false;
-      if (!upload_sync(d, h.data(), h.size())) return false;
+      if (!upload_sync(d, h.data(), bytes)) return false;
       M.d[ro][rA] = d;
-      M.words[ro][rA] = (int)(h.size() / 4);
+      M.words[ro][rA] = (int)(bytes / 4);
       M.ns[ro][rA] = ns;
     }
   njm[{dev, k}] = M;
