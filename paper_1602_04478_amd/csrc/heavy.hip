@@ -38,7 +38,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int CPER = 16;           // vertices per thread in a compaction chunk
+constexpr int CPER = 4;            // vertices per thread in a compaction chunk
 constexpr int CH = BLK * CPER;     // vertices per compaction chunk
 
 __device__ __forceinline__ int64_t nentries(const GroupDev &g, const LevelDev &L) {
