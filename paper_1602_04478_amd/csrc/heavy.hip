@@ -156,10 +156,9 @@ __global__ void k_mark_next(GraphDev g, GroupDev grp, LevelDev Lin, LevelDev Lou
         }
       }
       prd += 12;
-      if ((Lout.mb[2 * w] & mask) != mask) {
-        atomicOr((unsigned long long *)&Lout.mb[2 * w], (unsigned long long)mask);
-        pwr += 8;
-      }
+      // no read first: an atomic OR whose result is not used does not wait
+      atomicOr((unsigned long long *)&Lout.mb[2 * w], (unsigned long long)mask);
+      pwr += 8;
     }
   }
   prof_flush(grp.prof, prd, pwr, 0);
