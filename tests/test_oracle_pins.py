@@ -28,6 +28,23 @@ def test_colour_contract_c_equals_python():
             assert np.array_equal(O.colours(300, k, seed, t), O.colours_py(300, k, seed, t))
 
 
+def test_colour_is_the_hash_scaled_to_k():
+    """The colour is the hash read as a fraction of 2^64 and scaled to [0, k)
+    (its top 32 bits, so the floor may sit below by one when k*h lands within
+    k*2^32 above a multiple of 2^64): colours rise with the hash and each takes
+    one contiguous k-th of the hash range. A residue (h mod k) or a shift by the
+    wrong amount fails this on the first few vertices."""
+    n = 2000
+    for k, seed, t in ((2, 0, 0), (7, 102, 0), (12, 5, 3), (16, 2**63 + 17, 1)):
+        key = O.mix64((seed + t) & O.MASK64)
+        h = [O.mix64(key ^ v) for v in range(n)]
+        c = O.colours(n, k, seed, t)
+        for hv, cv in zip(h, c.tolist()):
+            assert cv * 2**64 <= k * hv < (cv + 1) * 2**64 + k * 2**32
+        order = np.argsort(np.array(h, dtype=np.uint64), kind="stable")
+        assert np.all(np.diff(c[order].astype(int)) >= 0)
+
+
 def test_colours_uniform_chi_square():
     k, n = 7, 200_000
     c = O.colours(n, k, 102)
