@@ -297,7 +297,10 @@ cc_status cc_last_solve_stats(cc_solve_stats *out);
  * are admitted while their device footprint fits the budget and fewer than
  * `max_inflight` are running; admitted requests run concurrently on a pool of
  * streams (continuous batching: a request arriving while others run starts as
- * soon as a stream slot and memory are free).  A request whose footprint
+ * soon as a stream slot and memory are free).  Requests start in arrival
+ * order, but while the oldest waiting one does not fit, later ones that fit
+ * may start ahead of it (at most 8 per waiting request, so none waits without
+ * bound).  A request whose footprint
  * exceeds the budget runs alone within the budget (smaller trial and source
  * groups).  Results are identical to cc_count on the same arguments.
  */

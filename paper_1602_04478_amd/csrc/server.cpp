@@ -1,8 +1,12 @@
 // Serving loop: requests (graph, query, seed, trials) against resident graphs.
 //
 // Admission is by device footprint: a request starts when a worker slot is
-// free and its footprint fits what the budget has left; otherwise it waits in
-// arrival order (a request that would never fit is run alone).  Each worker
+// free and its footprint fits what the budget has left (a request that would
+// never fit is run alone).  Requests start in arrival order, except that while
+// the oldest waiting request does not fit, a later one that fits may start
+// ahead of it, at most kMaxBypass times per waiting request; after that the
+// oldest one is next, so no request waits behind an unbounded stream of
+// smaller ones.  Each worker
 // owns a HIP stream, so admitted requests run concurrently on the device and a
 // request that arrives while others run starts as soon as a slot and memory
 // free up.  The arithmetic is exactly cc_count's, so a result does not depend
@@ -22,6 +26,9 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// how many later requests may start ahead of a waiting request that does not fit
+constexpr int kMaxBypass = 8;
+
 struct Request {
   uint64_t ticket;
   int graph;
@@ -29,6 +36,7 @@ struct Request {
   uint64_t seed;
   int trials;
   uint64_t bytes;
+  int bypassed = 0;  // later requests started ahead of this one
   Clock::time_point t_submit;
   // results
   bool done = false;
@@ -70,12 +78,23 @@ struct cc_server_s {
             return;
           }
           if (!queue.empty()) {
-            Request &r = reqs[queue.front()];
-            bool fits = in_use + r.bytes <= budget || running == 0;
-            if (fits) {
-              tk = queue.front();
-              queue.pop_front();
-              in_use += r.bytes;
+            Request &h = reqs[queue.front()];
+            auto it = queue.end();
+            if (in_use + h.bytes <= budget || running == 0) {
+              it = queue.begin();
+            } else if (h.bypassed < kMaxBypass) {
+              // the oldest request waits for memory: start the first later one that fits
+              for (auto j = queue.begin() + 1; j != queue.end(); ++j)
+                if (in_use + reqs[*j].bytes <= budget) {
+                  it = j;
+                  h.bypassed++;
+                  break;
+                }
+            }
+            if (it != queue.end()) {
+              tk = *it;
+              queue.erase(it);
+              in_use += reqs[tk].bytes;
               running++;
               break;
             }
