@@ -895,6 +895,60 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
               }
             }
           }
+        } else if (ANN && T == 1 && epi.ann_lanes) {
+          // annotated, one trial: the output slots of a (neighbour, source)
+          // pair spread over the lanes (lane = (pair of the round, slot); rows
+          // wider than the group: one pair a round, SW slots a step), so a
+          // neighbour that relaxes few sources still keeps the lanes busy.
+          // Each (source, slot) column has one writer per round: plain adds.
+          const int NY = C <= SW ? SW / C : 1;  // pairs per round
+          const int py = C <= SW ? gl / C : 0, co0 = C <= SW ? gl - py * C : gl, cstep = C <= SW ? C : SW;
+          const bool lane_on = py < NY;
+          const int cwq = colr[w];  // w's colour (cw is set only on lanes that hold a source)
+          while (todo) {
+            const int jj = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int v = __shfl(vj, jj, SW);
+            const uint64_t ib = __shfl(inb, jj, SW);
+            const uint64_t mf = grp.dense ? 0 : __shfl(mfull, jj, SW);
+            const int64_t vb = grp.dense ? 0 : __shfl(bj, jj, SW);
+            const int cv = __shfl(cvj, jj, SW);
+            // the group's lanes whose sources relax a row from v
+            uint64_t M = gballot(act && v < ub && ((ib >> b) & 1ull) && cv != cu && cv != cw);
+            if (!M) continue;
+            const int64_t es = j0 + jj;
+            const int64_t tslot = e_src_first ? g.rev[es] : es;
+            const uint64_t *er = et.val + tslot * et.C;
+            while (M) {
+              const int nm = __popcll(M);
+              const int lpos = lane_on && py < nm ? nth_set_bit(M, py) : -1;  // this lane's pair: its source's lane
+              if (nm <= NY) M = 0;
+              else M &= ~((2ull << nth_set_bit(M, NY - 1)) - 1ull);  // the bit is below 63: more follow it
+              const int bq = __shfl(b, lpos < 0 ? 0 : lpos, SW), cuq = __shfl(cu, lpos < 0 ? 0 : lpos, SW);
+              if (lpos < 0) continue;
+              const int64_t id = grp.dense ? (int64_t)v * B + bq : vb + __popcll(mf & ((1ull << bq) - 1ull));
+              if (co0 == 0) n_rows++;
+              const uint64_t *row = a.val + id * Ca;
+              for (int co = co0; co < C; co += cstep) {
+                const uint32_t Rp = spread2(s_um[co], cuq, cwq);
+                if (!((Rp >> cv) & 1u)) continue;
+                const uint32_t R = Rp & ~(1u << cv);
+                const int nR = __popc(R);
+                if (ra > nR) continue;
+                uint64_t sum = 0;
+                // the subsets of R of size ra (the input row's colours)
+                for (uint32_t cm = (1u << ra) - 1u; cm < (1u << nR); cm = ra ? next_comb(cm) : (1u << nR)) {
+                  const uint32_t s1 = deposit(cm, R);
+                  const uint64_t xa = row[s_rank[squeeze2(s1, cuq, cv)]];
+                  if (xa) {
+                    const uint64_t y = er[s_rank[squeeze2(R & ~s1, cv, cwq)]];
+                    if (y) add_ck(sum, mul_ck(xa, y, of), of);
+                  }
+                }
+                if (sum) add_ck(acc[co * NB + (tid - gl) + lpos], sum, of);
+              }
+            }
+          }
         } else {
           while (todo) {
             const int jj = __builtin_ctzll(todo);
@@ -935,7 +989,8 @@ __global__ __launch_bounds__(NB, MAP && !EPI ? (SW == 16 ? EJ_MINW_SPARSE : PACK
         }
         if (stop) break;
       }
-      if (PACK) __threadfence_block();  // other lanes' LDS atomics into this lane's column are done
+      // other lanes' adds into this lane's columns are done
+      if (PACK || (ANN && T == 1 && epi.ann_lanes)) __threadfence_block();
       // epilogue: row-local ops on the rows of w, operands in LDS or read
       // from global memory at their own level
       if (EPI && b >= 0 && epi.nops) {
@@ -2156,7 +2211,7 @@ __global__ __launch_bounds__(BLK) void k_munary(GroupDev grp, int64_t n, const u
   const int ra = a.s - 2;
   const int64_t per = (int64_t)T * C_out;
   const int64_t N = nentries(grp, La) * per;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;  // profile: bytes read, written
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     const int64_t e = i / per;
     const int r = (int)(i - e * per), t = r / C_out, c = r - t * C_out;
@@ -2170,6 +2225,7 @@ __global__ __launch_bounds__(BLK) void k_munary(GroupDev grp, int64_t n, const u
     const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
     if (cu == cv) continue;
     const int ckey = at_u ? cu : cv, coth = at_u ? cv : cu;
+    if (c == 0) prd += 8 * (uint64_t)(Ca + Cb);  // both rows, once per (entry, trial)
     const uint32_t Rq = spread1(unrank(lut, s_out - 1, c), ckey);
     if (!((Rq >> coth) & 1u)) continue;
     const uint32_t R = Rq & ~(1u << coth);
@@ -2189,10 +2245,14 @@ __global__ __launch_bounds__(BLK) void k_munary(GroupDev grp, int64_t n, const u
       if (s1 == 0) break;
       s1 = (s1 - 1) & R;
     }
-    if (s) atomic_add_ck(&out[((at_u ? u : v) * T + t) * C_out + c], mul_ck(s, w, of), of);
+    if (s) {
+      atomic_add_ck(&out[((at_u ? u : v) * T + t) * C_out + c], mul_ck(s, w, of), of);
+      pwr += 8;
+    }
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // ------------------------------------------------------------------ pair-keyed merges
@@ -2210,7 +2270,7 @@ __global__ __launch_bounds__(BLK) void k_mpair(GroupDev grp, int64_t n, const ui
   const int ra = a.s - 2;
   const int64_t per = (int64_t)T * C;
   const int64_t N = grp.n_lim * (int64_t)grp.B * per;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;  // profile: bytes read, written (every staged slot)
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     const int64_t row = i / per;
     const int r = (int)(i - row * per), t = r / C, c = r - t * C;
@@ -2222,6 +2282,7 @@ __global__ __launch_bounds__(BLK) void k_mpair(GroupDev grp, int64_t n, const ui
     if (v != u && live(grp, a, v, b) && live(grp, bb, v, b)) {
       const int cu = colr[(int64_t)t * n + u], cv = colr[(int64_t)t * n + v];
       if (cu != cv) {
+        if (c == 0) prd += 8 * (uint64_t)(Ca + Cb);  // both rows, once per (row, trial)
         const uint32_t R = spread2(unrank(lut, dst.s - 2, c), cu, cv);
         const uint64_t *ar = a.val + (row * T + t) * Ca;
         const uint64_t *br = bb.val + (row * T + t) * Cb;
@@ -2241,10 +2302,12 @@ __global__ __launch_bounds__(BLK) void k_mpair(GroupDev grp, int64_t n, const ui
       }
     }
     dst.val[i] = sum;
+    pwr += 8;
     if (sum) atomicOr((unsigned long long *)&dst.mask[v], 1ull << b);
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // Append the nonzero staged rows as pair-table entries: keys (u_b, v),
@@ -2290,7 +2353,7 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
   const int ra = a.s - 2, rb = bb.s - 2;
   const int64_t per = (int64_t)T * C_out;
   const int64_t N = nentries(grp, La) * per;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;  // profile: bytes read, written
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     const int64_t e = i / per;
     const int r = (int)(i - e * per), t = r / C_out, c = r - t * C_out;
@@ -2302,14 +2365,17 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
     const int cu = colr[(int64_t)t * g.n + u], cx = colr[(int64_t)t * g.n + x];
     if (cu == cx) continue;
     const uint64_t *ar = a.val + (e * T + t) * Ca;
+    if (c == 0) prd += 8 * (uint64_t)Ca;  // a's row, once per (entry, trial)
     bool of = false;
     for (int64_t ee = g.rp[x]; ee < g.rp[x + 1]; ee++) {
       const int64_t y = g.col[ee];
       if (y >= vbound(grp, u)) break;
+      if (c == 0) prd += 4;  // the neighbour id
       const int64_t eb = row_of(grp, Lb, bb, y, b);
       if (eb < 0) continue;
       const int cy = colr[(int64_t)t * g.n + y];
       if (cy == cx || cy == cu) continue;
+      if (c == 0) prd += 8 * (uint64_t)(Cb + (et.val ? et.C : 0));  // b's row and the edge's
       const uint32_t Rp = spread2(unrank(lut, s_out - 2, c), cx, cy);
       if (!((Rp >> cu) & 1u)) continue;
       const uint32_t R = Rp & ~(1u << cu);
@@ -2342,11 +2408,13 @@ __global__ __launch_bounds__(BLK) void k_medge(GraphDev g, GroupDev grp, const u
       if (s) {
         const int64_t oslot = out_first_is_x ? ee : g.rev[ee];
         atomic_add_ck(&out[(oslot * T + t) * C_out + c], mul_ck(s, w, of), of);
+        pwr += 8;
       }
     }
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // The same merge vertex-major: a wavefront owns a vertex x with all the
@@ -2379,7 +2447,7 @@ __global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const
   const bool lane_on = yl < NY;
   const uint64_t bmask = B >= 64 ? ~0ull : (1ull << B) - 1ull;
   const int64_t n = g.n;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;  // profile: bytes read, written
   const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + threadIdx.x / 64, nwave = (int64_t)gridDim.x * (BLK / 64);
   const int64_t nitems = DENSE ? grp.n_lim : (int64_t)La.cnt[1];
   for (int64_t it = wave; it < nitems; it += nwave) {
@@ -2406,6 +2474,7 @@ __global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const
       const int64_t ee = j0 + lane;
       int y = ee < r1 ? g.col[ee] : VNONE;
       if (y >= umax || (DENSE && y >= grp.n_lim)) y = VNONE;  // ascending: the later ones too
+      if (grp.prof && y != VNONE) prd += 4;  // the neighbour id
       uint64_t Bm = 0;
       int64_t bbase = 0;
       if (y != VNONE) {
@@ -2437,6 +2506,7 @@ __global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const
         if (!lane_on || jn < 0) continue;
         const int cy = colr[(int64_t)t * n + yv];
         if (cy == cx) continue;
+        if (grp.prof && c == 0 && et.val) prd += 8 * (uint64_t)et.C;  // the edge's row
         const uint32_t Rp = spread2(s_uo[c], cx, cy);
         const int64_t es = j0 + jn;
         const int64_t tslot = e_src_first ? es : g.rev[es];
@@ -2446,7 +2516,9 @@ __global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const
           const int b = __builtin_ctzll(q);
           if (yv >= s_bnd[b]) continue;
           const int cu = s_cu[t * WAVE + b];
-          if (cu == cx || cu == cy || !((Rp >> cu) & 1u)) continue;
+          if (cu == cx || cu == cy) continue;
+          if (grp.prof && c == 0) prd += 8 * (uint64_t)(Ca + Cb);  // both rows, once per (source, edge, trial)
+          if (!((Rp >> cu) & 1u)) continue;
           const uint32_t R = Rp & ~(1u << cu);
           const uint64_t lowb = (1ull << b) - 1ull;
           const int64_t ea = DENSE ? (int64_t)x * B + b : abase + __popcll(Aall & lowb);
@@ -2481,6 +2553,7 @@ __global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const
         if (sum) {
           const int64_t oslot = out_first_is_x ? es : g.rev[es];
           atomic_add_ck(&out[(oslot * T + t) * C_out + c], mul_ck(sum, w, of), of);
+          pwr += 8;
         }
       }
       if (stop) break;
@@ -2488,6 +2561,7 @@ __global__ __launch_bounds__(BLK) void k_medge_v(GraphDev g, GroupDev grp, const
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 // T[u,y] += w * A[u][Ra] * E(u,y)[Re] * b[(y,b)][R2] over the lower neighbours y of u_b.
@@ -2502,7 +2576,7 @@ __global__ __launch_bounds__(BLK) void k_medge_t(GraphDev g, GroupDev grp, const
   const int rA = nt.val ? nt.s - 1 : 0, rb = bb.s - 2;
   const int64_t per = (int64_t)T * C_out;
   const int64_t N = (int64_t)grp.B * max_low * per;
-  uint64_t ofm = 0;
+  uint64_t ofm = 0, prd = 0, pwr = 0;  // profile: bytes read, written
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLK) {
     const int64_t en = i / per;
     const int r = (int)(i - en * per), t = r / C_out, c = r - t * C_out;
@@ -2515,6 +2589,8 @@ __global__ __launch_bounds__(BLK) void k_medge_t(GraphDev g, GroupDev grp, const
     if (eb < 0) continue;
     const int cu = colr[(int64_t)t * g.n + u], cy = colr[(int64_t)t * g.n + y];
     if (cu == cy) continue;
+    // b's row, the edge's and the node table's, once per (source, edge, trial)
+    if (c == 0) prd += 8 * (uint64_t)(Cb + (et.val ? et.C : 0) + (nt.val ? nt.C : 0));
     const uint32_t R = spread2(unrank(lut, s_out - 2, c), cu, cy);
     const uint64_t *br = bb.val + (eb * T + t) * Cb;
     const int64_t tslot = e_src_first ? es : g.rev[es];
@@ -2547,10 +2623,12 @@ __global__ __launch_bounds__(BLK) void k_medge_t(GraphDev g, GroupDev grp, const
     if (s) {
       const int64_t oslot = out_first_is_u ? es : g.rev[es];
       atomic_add_ck(&out[(oslot * T + t) * C_out + c], mul_ck(s, w, of), of);
+      pwr += 8;
     }
     if (of) ofm |= 1ull << t;
   }
   flag_trials(ovf, ofm);
+  prof_flush(grp.prof, prd, pwr, 0);
 }
 
 const uint16_t *cur_lut() {
@@ -2764,7 +2842,9 @@ static bool njmap_find(int k, int ro, int rA, int C, int Ca, int Cn, const uint3
 }
 
 void launch_ej_epi(const GraphDev &g, const GroupDev &grp, const uint8_t *colr, LevelDev Lin, RegDev a,
-                   const Epilogue &epi, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st) {
+                   const Epilogue &epi_in, TabDev etab, int e_src_first, uint32_t *ovf, AccDev acc, hipStream_t st) {
+  Epilogue epi = epi_in;
+  epi.ann_lanes = getenv_flag_off("CC_EJANNLANES") ? 0 : 1;
   const bool ep = epi.nops > 0;
   if (!ep && grp.dense && grp.nh > 0 && grp.split_lo < grp.n_lim) {
     // the hubs' rows and activity words start at zero: their chunks add into them

@@ -117,6 +117,9 @@ struct Epilogue {
   RegDev in2;
   const uint32_t *map2;
   int map2_w, map2_cp;
+  // annotated EdgeJoins with one trial: 1 = a pair's output slots spread
+  // over the lanes, 0 = one source per lane (set by the launch)
+  int ann_lanes;
 };
 
 const uint16_t *lut_device(int device);

@@ -110,6 +110,9 @@ ONE_TRIAL_MODES = {
     # the AXPY chains one slot per lane with gathers instead of rows staged in LDS
     "dense-axpy-slots": {"CC_DENSE": "all", "CC_AXPY_ROWS": "0"},
     "sparse-axpy-slots": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_AXPY_ROWS": "0"},
+    # annotated EdgeJoins one source per lane (not a pair's slots over the lanes)
+    "dense-ann-per-source": {"CC_DENSE": "all", "CC_EJANNLANES": "0"},
+    "sparse-ann-per-source": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJANNLANES": "0"},
 }
 
 

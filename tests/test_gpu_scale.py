@@ -140,6 +140,30 @@ def test_generated_queries():
                 assert int(counts[16 * i + t]) == want and not ovf[16 * i + t], (i, gq["family"], t)
 
 
+@pytest.mark.parametrize("mode", ["dense", "sparse", "dense-ann-per-source"])
+def test_generated_queries_one_trial(mode, monkeypatch):
+    """The generated queries of 9-10 nodes of the C4 shape at n = 1000, one
+    colouring per call (rows up to 70 slots: annotated EdgeJoins whose rows
+    are wider than a lane group spread a pair's slots over several steps)."""
+    env = {"dense": {"CC_DENSE": "all"}, "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"},
+           "dense-ann-per-source": {"CC_DENSE": "all", "CC_EJANNLANES": "0"}}[mode]
+    for key, val in env.items():
+        monkeypatch.setenv(key, val)
+    g = graphs.chung_lu(1000, 8.0, 2.1, None, seed=4)
+    dg = cc.Graph.from_csr(g)
+    gold = _gold("c4_scaled")["queries"]
+    qs = Q.random_queries(204, 20, 4, 10)
+    for i, ((k, E, fam), gq) in enumerate(zip(qs, gold)):
+        if k < 9:
+            continue
+        q = cc.Query(k, E)
+        print(f"[scale] generated query {i} ({fam}, k={k}), one colouring, mode {mode}", flush=True)
+        for t in range(2):
+            counts, ovf, exact, est = cc.count(dg, q, gq["seed"] + t, 1)
+            want = int(gq["counts"][t])
+            assert int(exact[0]) == want, (i, fam, t, int(exact[0]), want)
+
+
 def _star_forest(hubs, leaves):
     e = []
     n = hubs * (leaves + 1)
