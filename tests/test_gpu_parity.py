@@ -113,6 +113,9 @@ ONE_TRIAL_MODES = {
     # annotated EdgeJoins one source per lane (not a pair's slots over the lanes)
     "dense-ann-per-source": {"CC_DENSE": "all", "CC_EJANNLANES": "0"},
     "sparse-ann-per-source": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_EJANNLANES": "0"},
+    # the fused EdgeJoin epilogues with one colouring (annotated joins: slots over the lanes, then the epilogue)
+    "dense-fused": {"CC_DENSE": "all", "CC_FUSE": "1"},
+    "sparse-fused": {"CC_DENSE": "none", "CC_LIGHT": "0", "CC_FUSE": "1"},
 }
 
 
