@@ -83,7 +83,7 @@ KERNEL_OF = {  # profiled op name -> the HIP kernel (or the kernels, one per lau
     "edgejoin": "k_ejv", "edgejoin2": "k_ejv", "nodejoin": "k_nj / k_nj_dense",
     "axpy": "k_axpyn_rows / k_axpyn / k_axpyn_dense", "merge_root": "k_mroot_rows / k_mroot", "init": "k_init",
     "merge_u": "k_munary", "merge_v": "k_munary", "merge_edge": "k_medge_v / k_medge", "merge_edge_t": "k_medge_t",
-    "level_build_sparse": "level build", "light": "k_light", "light_large": "k_light", "leaf": "k_leaf",
+    "level_build": "k_mark_* / k_cmp_*", "light": "k_light", "light_large": "k_light", "leaf": "k_leaf",
     "root_single": "k_root_single", "merge_root_terms": "k_mroot_rows / k_mroot_terms", "merge_pair": "k_mpair",
 }
 
