@@ -286,3 +286,48 @@ def test_every_tree_same_count(small_graphs):
         for t in range(min(nt, 12)):
             print(f"[parity] {name} tree {t} of {nt}", flush=True)
             assert cc.count_colors(dg, cc.Query(k, E, tree=t), col)[2][0] == want, (name, t)
+
+
+def _degenerate_graphs():
+    def kbip(a, b):
+        return graphs.from_edges(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+    return {
+        "edgeless": graphs.from_edges(40, np.zeros((0, 2), dtype=np.int64)),
+        "fewer-vertices-than-k": graphs.from_edges(3, [(0, 1), (1, 2), (2, 0)]),
+        "bipartite-K66": kbip(6, 6),
+        "path30": graphs.from_edges(30, [(i, i + 1) for i in range(29)]),
+        "star20": graphs.from_edges(21, [(0, i) for i in range(1, 21)]),
+        "clique-and-isolated": graphs.from_edges(20, [(i, j) for i in range(6) for j in range(i + 1, 6)]
+                                                 + [(10, 11), (11, 12)]),
+        "one-edge": graphs.from_edges(2, [(0, 1)]),
+    }
+
+
+DEGENERATE_SHAPES = ["C3", "C4", "C5", "star5", "path4", "edge", "C6+pendant", "bowtie"]
+
+
+@pytest.mark.parametrize("mode", ["auto", "dense", "sparse"])
+def test_degenerate_graphs(mode, monkeypatch):
+    """Graphs with no edges, fewer vertices than query nodes, no odd cycles
+    (bipartite), trees, a star, isolated vertices beside a clique and a
+    single edge: counts equal the oracle's, zero wherever no match exists
+    (an odd cycle in a bipartite graph, any cycle in a tree, anything in an
+    edgeless graph), on every execution path and with device colours."""
+    env = {"auto": {}, "dense": {"CC_DENSE": "all"}, "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"}}[mode]
+    for key, val in env.items():
+        monkeypatch.setenv(key, val)
+    for gname, g in _degenerate_graphs().items():
+        dg = cc.Graph.from_csr(g)
+        for name in DEGENERATE_SHAPES:
+            k, E = SHAPES[name]
+            q = cc.Query(k, E)
+            print(f"[parity] degenerate {gname} n={g.n} m={g.m} {name} mode={mode}", flush=True)
+            chi = O.colours(g.n, k, 77, 0)
+            want = O.db(g, k, E, chi)
+            if g.m == 0 or g.n < k or (gname in ("bipartite-K66",) and name in ("C3", "C5", "bowtie")) \
+                    or (gname in ("path30", "star20") and name in ("C3", "C4", "C5", "bowtie", "C6+pendant")):
+                assert want == 0
+            counts, ovf, exact = cc.count_colors(dg, q, chi[None, :])
+            assert exact[0] == want and int(counts[0]) == want and not ovf[0], (gname, name, exact[0], want)
+            c2, o2, e2, est = cc.count(dg, q, 77, 1)
+            assert int(e2[0]) == want, (gname, name, int(e2[0]), want)
