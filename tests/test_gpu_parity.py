@@ -331,3 +331,33 @@ def test_degenerate_graphs(mode, monkeypatch):
             assert exact[0] == want and int(counts[0]) == want and not ovf[0], (gname, name, exact[0], want)
             c2, o2, e2, est = cc.count(dg, q, 77, 1)
             assert int(e2[0]) == want, (gname, name, int(e2[0]), want)
+
+
+LARGEST_QUERIES = {
+    "C12": Q.cycle(12),
+    "C11+pendant": Q.cycle_pendant(11),
+    "C12+chord": (12, [(i, (i + 1) % 12) for i in range(12)] + [(0, 6)]),
+    "C6+tree": (12, [(i, (i + 1) % 6) for i in range(6)] + [(5, 6), (6, 7), (7, 8), (6, 9), (9, 10), (10, 11)]),
+}
+
+
+@pytest.mark.parametrize("mode", ["auto", "dense", "sparse"])
+def test_largest_queries(mode, monkeypatch):
+    """Queries of 12 nodes, the largest the planner takes (rows of up to
+    C(10, 5) = 252 slots: the entry-major EdgeJoin and no slot maps), on an
+    80-vertex random graph: two colourings per call and one, against the
+    oracle."""
+    env = {"auto": {}, "dense": {"CC_DENSE": "all"}, "sparse": {"CC_DENSE": "none", "CC_LIGHT": "0"}}[mode]
+    for key, val in env.items():
+        monkeypatch.setenv(key, val)
+    g = graphs.erdos_renyi(80, 6.0, seed=12)
+    dg = cc.Graph.from_csr(g)
+    for name, (k, E) in LARGEST_QUERIES.items():
+        q = cc.Query(k, E)
+        chi = np.stack([O.colours(g.n, k, 91, t) for t in range(2)])
+        want = [O.db(g, k, E, chi[t]) for t in range(2)]
+        print(f"[parity] largest {name} k={k} mode={mode}", flush=True)
+        counts, ovf, exact = cc.count_colors(dg, q, chi)
+        assert [int(x) for x in exact] == want and not ovf.any(), (name, mode, exact, want)
+        one = cc.count_colors(dg, q, chi[1:2])[2]
+        assert int(one[0]) == want[1], (name, mode, int(one[0]), want[1])
